@@ -1,0 +1,144 @@
+/*
+ * nmf.h -- C ABI of the MI355X (gfx950) multiplicative-update NMF library.
+ *
+ * The library factors a nonnegative matrix V (p x n) as W (p x r) times
+ * H (r x n) by the multiplicative majorize-minimize updates of Zhou, Lange &
+ * Suchard, "Graphics Processing Units and High-Dimensional Optimization",
+ * Sec. 3.1 (eq. nnmf-objfn, eq. nnmf_v_update, eq. nnmf_w_update,
+ * Algorithm 1 NNMF).  The paper writes X ~ V W; this header writes V ~ W H,
+ * so the paper's "V update" is the W update here and its "W update" is the
+ * H update here.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major float32.  V has row stride ldv (in elements,
+ *     ldv >= n); W is p x r with row stride r; H is r x n with row stride n.
+ *   - Pointers named V, W, H, W0, H0 are DEVICE pointers (hipMalloc'd or
+ *     torch CUDA tensors); pointers named *_host are host pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All work is enqueued on that stream; entry points that return a value
+ *     to the host synchronize it.
+ *   - Errors are reported only through the return code; no entry point
+ *     aborts or throws.  Argument checks happen before any device work, so
+ *     an NMF_EINVAL return has no side effects.
+ *   - The caller owns V, W and H.  V is never written.  W and H are updated
+ *     in place by every iteration.  The context owns only its workspace,
+ *     which nmf_destroy releases.  No entry point frees caller memory.
+ *   - A context is not thread-safe; use one context per host thread.
+ *     Results are deterministic: no floating-point atomics are used, and
+ *     all reductions run in a fixed order for a given shape and precision.
+ */
+#ifndef NMF_H
+#define NMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmf_ctx nmf_ctx;
+
+typedef enum {
+  NMF_OK = 0,
+  NMF_ENOTCONVERGED = 1,  /* iteration cap reached; the state is valid       */
+  NMF_EINVAL = -1,        /* bad argument, or V failed validation            */
+  NMF_ENOMEM = -2,        /* device allocation failed                        */
+  NMF_EDEVICE = -3,       /* a HIP runtime call failed                       */
+  NMF_ENONFINITE = -4,    /* the objective became NaN or Inf                 */
+  NMF_EUNSUPPORTED = -5   /* r above NMF_MAX_RANK, or an unknown option      */
+} nmf_status;
+
+typedef enum {
+  NMF_FP32 = 0,  /* float32 operands, float32 accumulation                   */
+  NMF_BF16 = 1   /* bfloat16 (round-to-nearest-even) copies of V, W, H and
+                    the Grams feed the products; float32 accumulation and
+                    float32 master factors                                  */
+} nmf_precision;
+
+typedef enum {
+  /* |f_k - f_prev| / (|f_prev| + 1) < tol, f_prev the objective at the
+     previous check: the stopping rule of Sec. 3 (introduction of the
+     numerical examples), which uses tol = 1e-9 and checks every iteration. */
+  NMF_TOL_REL_CHANGE = 0,
+  /* f_k / ||V||_F^2 <= tol (relative objective gap against f* = 0).         */
+  NMF_TOL_GAP_NORMALIZED = 1
+} nmf_tol_kind;
+
+#define NMF_MAX_RANK 256
+
+typedef struct {
+  int32_t precision;    /* nmf_precision                                    */
+  int32_t tol_kind;     /* nmf_tol_kind                                     */
+  double tol;           /* tolerance of the stopping rule                   */
+  int32_t check_every;  /* iterations between objective checks (>= 1)       */
+  int32_t validate;     /* nonzero: nmf_init scans V and rejects negative or
+                           non-finite entries with NMF_EINVAL               */
+  uint64_t seed;        /* nonzero: nmf_init overwrites W and H with
+                           U(0,1) draws from a counter-based Philox4x32-10
+                           generator keyed by seed (Algorithm 1's
+                           initialization); zero: start from the caller's
+                           W and H                                          */
+} nmf_options;
+
+/* Fill *opt with defaults: FP32, REL_CHANGE, tol 1e-9, check_every 1,
+   validate 0, seed 0.  NULL is ignored. */
+void nmf_default_options(nmf_options* opt);
+
+/* Create a context for V (p x n, row stride ldv) and rank r, reading the
+   starting factors from W (p x r) and H (r x n) unless opt->seed != 0, in
+   which case W and H are filled on the device.  Computes the r x r Gram
+   H H^T of the start.  opt may be NULL (defaults).  p, n, r >= 1,
+   r <= NMF_MAX_RANK, ldv >= n; V, W, H non-NULL and 4-byte aligned.
+   V, W and H must stay allocated until nmf_destroy, and the caller must not
+   write W or H while the context exists (call nmf_init again to restart
+   from new factors).  On success *out receives the context; on failure
+   *out is set to NULL. */
+nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n,
+                    int64_t ldv, int32_t r, float* W, float* H,
+                    const nmf_options* opt, void* stream);
+
+/* Enqueue `iters` (>= 0) full iterations of Algorithm 1 (NNMF): the W
+   update of eq. nnmf_v_update followed by the H update of eq.
+   nnmf_w_update with the new W.  Asynchronous; no host synchronization. */
+nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
+
+/* Enqueue only the W half-step (eq. nnmf_v_update):
+   W <- W * (V H^T) / (W (H H^T)), entries with a non-positive denominator
+   kept unchanged.  Asynchronous. */
+nmf_status nmf_update_w(nmf_ctx* ctx);
+
+/* Enqueue only the H half-step (eq. nnmf_w_update) with the current W:
+   H <- H * (W^T V) / ((W^T W) H), guarded as above.  Asynchronous. */
+nmf_status nmf_update_h(nmf_ctx* ctx);
+
+/* Objective f = ||V - W H||_F^2 (eq. nnmf-objfn) from the current W and H:
+   direct residual, products and sums in float64 on the device, reduced in a
+   fixed order.  Synchronizes the stream and writes *f_host.
+   Returns NMF_ENONFINITE (with *f_host set) if f is NaN or Inf. */
+nmf_status nmf_objective(nmf_ctx* ctx, double* f_host);
+
+/* Iterate until the stopping rule of the context's options holds or
+   max_iters iterations have run.  The objective is evaluated at the start
+   and after every check_every iterations (and after the last one).
+   *iters_done_host receives the number of iterations run and *f_host the
+   last objective.  trace_host (may be NULL) receives the evaluated
+   objectives, f_0 first, up to trace_len entries.  Returns NMF_OK when the
+   rule held, NMF_ENOTCONVERGED at the cap, NMF_ENONFINITE if f became
+   non-finite. */
+nmf_status nmf_solve(nmf_ctx* ctx, int32_t max_iters, int32_t* iters_done_host,
+                     double* f_host, double* trace_host, int32_t trace_len);
+
+/* Release the context's workspace.  NULL is ignored. */
+void nmf_destroy(nmf_ctx* ctx);
+
+/* Static description of a status code. */
+const char* nmf_strerror(nmf_status s);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t nmf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMF_H */

@@ -1,0 +1,111 @@
+// Internal interface between the host runtime (nmf_runtime.hip) and the
+// gfx950 kernels (nmf_kernels.hip).  Each launcher enqueues one kernel on
+// `st` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nmfk {
+
+// Supported padded ranks: the rank dimension of every internal buffer is
+// padded with zeros to one of these.
+inline int padded_rank(int r) {
+  if (r <= 16) return 16;
+  if (r <= 32) return 32;
+  if (r <= 64) return 64;
+  if (r <= 128) return 128;
+  return 256;
+}
+
+// Tile shape of the "NT" product  C[m][c] = sum_k X[m][k] * Y[c][k]
+// (both operands contiguous along k).  BM x BN output tile per workgroup.
+struct NtCfg {
+  int id;      // template instance
+  int bm, bn;  // tile
+  int threads;
+};
+// Tile shape of the "TN" product  C[m][c] = sum_k A[k][m] * B[k][c]
+// (both operands contiguous along the output dimension, k the row index).
+struct TnCfg {
+  int id;
+  int bm, bn;
+  int threads;
+};
+
+NtCfg nt_config(int rp, bool gram);
+TnCfg tn_config(int rp, bool gram);
+NtCfg nt_bf16_config(int rp, bool gram);
+
+// ---- FP32 products with split-K partials --------------------------------
+// part[s][m][c] (row pitch ldp, split pitch sp) for m < round_up(M, bm),
+// c < round_up(N, bn).  Rows m >= M / k >= K read as zero.
+hipError_t launch_gemm_nt(const NtCfg& cfg, const float* X, int64_t ldx,
+                          int64_t M, const float* Y, int64_t ldy, int64_t N,
+                          int64_t K, int splits, int64_t kchunk, float* part,
+                          int64_t ldp, int64_t sp, hipStream_t st);
+hipError_t launch_gemm_tn(const TnCfg& cfg, const float* A, int64_t lda,
+                          int64_t M, const float* B, int64_t ldb, int64_t N,
+                          int64_t K, int splits, int64_t kchunk, float* part,
+                          int64_t ldp, int64_t sp, hipStream_t st);
+
+// ---- BF16 NT product (16x16x32 MFMA, FP32 accumulation) ------------------
+hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X,
+                               int64_t ldx, int64_t M, const uint16_t* Y,
+                               int64_t ldy, int64_t N, int64_t K, int splits,
+                               int64_t kchunk, float* part, int64_t ldp,
+                               int64_t sp, hipStream_t st);
+
+// G[m][c] = sum_s part[s][m][c] for m, c < rp; written with pitch rp.
+// With bf16 != nullptr also writes the bfloat16 rounding of G there.
+hipError_t launch_reduce_gram(const float* part, int64_t ldp, int64_t sp,
+                              int splits, int rp, float* G, uint16_t* Gbf,
+                              hipStream_t st);
+
+// W half-step epilogue.  Wp (ppad x rp) holds the current W; A partials are
+// part[s][i][k] (pitch ldp, split pitch sp).  Writes the new W to Wp, to the
+// caller's W (p x r) and, for the BF16 tier, to WbT (rp x ldwt, transposed).
+hipError_t launch_update_w(int rp, int64_t p, int r, const float* part,
+                           int64_t ldp, int64_t sp, int splits, const float* G,
+                           float* Wp, float* Wcaller, uint16_t* WbT,
+                           int64_t ldwt, bool bf16, hipStream_t st);
+
+// H half-step epilogue.  Hp (rp x ldh) holds the current H.  S partials are
+// part[s][k][j] (transposed == false) or part[s][j][k] (transposed == true).
+// Writes Hp, the caller's H (r x n) and, for the BF16 tier, Hb (rp x ldh).
+hipError_t launch_update_h(int rp, int64_t n, int r, const float* part,
+                           int64_t ldp, int64_t sp, int splits,
+                           bool transposed, const float* G, float* Hp,
+                           int64_t ldh, float* Hcaller, uint16_t* Hb,
+                           bool bf16, hipStream_t st);
+
+// Objective partials: one double per 64 x 64 tile of V - W H.
+hipError_t launch_objective(int rp, const float* V, int64_t ldv, int64_t p,
+                            int64_t n, const float* Wp, const float* Hp,
+                            int64_t ldh, double* part, hipStream_t st);
+int64_t objective_parts(int64_t p, int64_t n);
+// out[0] = sum of part[0..count) in a fixed order.
+hipError_t launch_reduce_f64(const double* part, int64_t count, double* out,
+                             hipStream_t st);
+
+// Elementwise helpers.
+hipError_t launch_copy_pad(const float* src, int64_t lds, int64_t rows,
+                           int64_t cols, float* dst, int64_t ldd,
+                           hipStream_t st);  // dst[i][j] = src[i][j]
+hipError_t launch_fill_f32(float* dst, int64_t count, float v, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* dst, int64_t count, uint32_t v,
+                           hipStream_t st);
+// bf16 copy (RNE) of src (rows x cols) into dst with pitch ldd; with
+// transpose, dst[j][i] = bf16(src[i][j]).
+hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t rows,
+                            int64_t cols, uint16_t* dst, int64_t ldd,
+                            bool transpose, hipStream_t st);
+// flag |= 1 if some V entry is negative or non-finite.
+hipError_t launch_validate(const float* V, int64_t ldv, int64_t p, int64_t n,
+                           uint32_t* flag, hipStream_t st);
+// dst[i][j] = U(0,1) from Philox4x32-10(key = seed, counter = (i*cols + j,
+// stream_id, 0, 0)) for i < rows, j < cols; pitch ldd.
+hipError_t launch_uniform(float* dst, int64_t rows, int64_t cols, int64_t ldd,
+                          uint64_t seed, uint32_t stream_id, hipStream_t st);
+
+}  // namespace nmfk

@@ -1,0 +1,475 @@
+// Host runtime behind the C ABI of include/nmf.h: argument checks, device
+// workspace, tile/split selection and the per-iteration launch sequence of
+// Algorithm 1 (NNMF):
+//
+//   W half-step:  A = V H^T (split-K partials)  ->  W <- W * A / (W G_H)
+//                 -> G_W = W^T W                     (for the H half-step)
+//   H half-step:  S = W^T V (split-K partials)  ->  H <- H * S / (G_W H)
+//                 -> G_H = H H^T                     (for the next W half-step)
+//
+// Internal layout (row-major, zero padded):
+//   Wp   ppad x rp        ppad = round_up(p, 256), rp = padded rank
+//   Hp   rp x npad        npad = round_up(n, 256)
+//   G_H, G_W  rp x rp
+//   BF16 tier: Vb (p x ldvb) and VTb (n x ldvt) = bf16(V) and bf16(V^T),
+//              Hb (rp x npad), WbT (rp x ppad) = bf16(H) and bf16(W^T).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/nmf.h"
+#include "nmf_internal.h"
+
+using namespace nmfk;
+
+namespace {
+
+constexpr int64_t kMaxDim = 4000000;  // objective grid.y = ceil(p / 64) <= 65535
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct Split {
+  int splits = 1;
+  int64_t kchunk = 0;
+  int64_t ldp = 0;   // partial row pitch
+  int64_t rows = 0;  // partial rows
+  int64_t sp = 0;    // split pitch
+};
+
+// Split the reduction dimension K so that the grid has about `target`
+// workgroups while every split keeps at least `min_steps` stages of `bk`.
+Split plan_split(int64_t M, int64_t N, int64_t K, int bm, int bn, int bk, int64_t target,
+                 int64_t min_steps) {
+  Split s;
+  const int64_t tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+  const int64_t steps = (K + bk - 1) / bk;
+  int64_t want = std::max<int64_t>(1, target / std::max<int64_t>(1, tiles));
+  want = std::min<int64_t>(want, std::max<int64_t>(1, steps / min_steps));
+  want = std::min<int64_t>(want, 64);
+  const int64_t per = (steps + want - 1) / want;
+  s.kchunk = per * bk;
+  s.splits = (int)((K + s.kchunk - 1) / s.kchunk);
+  if (s.splits < 1) s.splits = 1;
+  s.rows = round_up(M, bm);
+  s.ldp = round_up(N, bn);
+  s.sp = s.rows * s.ldp;
+  return s;
+}
+
+}  // namespace
+
+struct nmf_ctx {
+  int device = 0;
+  hipStream_t st = nullptr;
+  int64_t p = 0, n = 0, ldv = 0;
+  int r = 0, rp = 0;
+  nmf_options opt{};
+  const float* Vuser = nullptr;
+  float* Wuser = nullptr;
+  float* Huser = nullptr;
+
+  const float* Vk = nullptr;  // V as read by the kernels
+  int64_t ldvk = 0;
+  int64_t ppad = 0, npad = 0;
+
+  // workspace (one allocation, carved)
+  void* ws = nullptr;
+  float* Vcopy = nullptr;
+  float* Wp = nullptr;
+  float* Hp = nullptr;
+  float* GH = nullptr;
+  float* GW = nullptr;
+  float* part1 = nullptr;
+  float* part2 = nullptr;
+  float* partg = nullptr;
+  double* fpart = nullptr;
+  double* fdev = nullptr;
+  uint32_t* flag = nullptr;
+  uint16_t* Vb = nullptr;
+  uint16_t* VTb = nullptr;
+  uint16_t* Hb = nullptr;
+  uint16_t* WbT = nullptr;
+  int64_t ldvb = 0, ldvt = 0;
+  double* hostbuf = nullptr;  // pinned, 2 doubles
+
+  bool bf16 = false;
+  NtCfg c1{}, cgh{}, c2b{};
+  TnCfg c2{}, cgw{};
+  Split s1, s2, sgh, sgw;
+  int64_t nparts = 0;
+  double nv2 = 0.0;  // ||V||_F^2 in float64
+};
+
+#define TRY_HIP(expr)                      \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return NMF_EDEVICE; \
+  } while (0)
+#define TRY(expr)                       \
+  do {                                  \
+    nmf_status s_ = (expr);             \
+    if (s_ != NMF_OK) return s_;        \
+  } while (0)
+
+namespace {
+
+nmf_status check_ptr(const void* p) {
+  if (!p) return NMF_EINVAL;
+  if (reinterpret_cast<uintptr_t>(p) % 4 != 0) return NMF_EINVAL;
+  return NMF_OK;
+}
+
+// Gram G_H = Hp Hp^T (or its bf16 analogue) from the current H.
+nmf_status gram_h(nmf_ctx* c) {
+  if (c->bf16) {
+    TRY_HIP(launch_gemm_nt_bf16(c->cgh, c->Hb, c->npad, c->rp, c->Hb, c->npad, c->rp, c->n,
+                                c->sgh.splits, c->sgh.kchunk, c->partg, c->sgh.ldp, c->sgh.sp,
+                                c->st));
+  } else {
+    TRY_HIP(launch_gemm_nt(c->cgh, c->Hp, c->npad, c->rp, c->Hp, c->npad, c->rp, c->n,
+                           c->sgh.splits, c->sgh.kchunk, c->partg, c->sgh.ldp, c->sgh.sp, c->st));
+  }
+  TRY_HIP(launch_reduce_gram(c->partg, c->sgh.ldp, c->sgh.sp, c->sgh.splits, c->rp, c->GH, nullptr,
+                             c->st));
+  return NMF_OK;
+}
+
+// Gram G_W = Wp^T Wp (or its bf16 analogue) from the current W.
+nmf_status gram_w(nmf_ctx* c) {
+  if (c->bf16) {
+    TRY_HIP(launch_gemm_nt_bf16(c->cgh, c->WbT, c->ppad, c->rp, c->WbT, c->ppad, c->rp, c->p,
+                                c->sgw.splits, c->sgw.kchunk, c->partg, c->sgw.ldp, c->sgw.sp,
+                                c->st));
+  } else {
+    TRY_HIP(launch_gemm_tn(c->cgw, c->Wp, c->rp, c->rp, c->Wp, c->rp, c->rp, c->p, c->sgw.splits,
+                           c->sgw.kchunk, c->partg, c->sgw.ldp, c->sgw.sp, c->st));
+  }
+  TRY_HIP(launch_reduce_gram(c->partg, c->sgw.ldp, c->sgw.sp, c->sgw.splits, c->rp, c->GW, nullptr,
+                             c->st));
+  return NMF_OK;
+}
+
+nmf_status half_w(nmf_ctx* c) {
+  if (c->bf16) {
+    TRY_HIP(launch_gemm_nt_bf16(c->c1, c->Vb, c->ldvb, c->p, c->Hb, c->npad, c->rp, c->n,
+                                c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, c->st));
+  } else {
+    TRY_HIP(launch_gemm_nt(c->c1, c->Vk, c->ldvk, c->p, c->Hp, c->npad, c->rp, c->n, c->s1.splits,
+                           c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, c->st));
+  }
+  TRY_HIP(launch_update_w(c->rp, c->p, c->r, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits, c->GH,
+                          c->Wp, c->Wuser, c->bf16 ? c->WbT : nullptr, c->ppad, c->bf16, c->st));
+  return gram_w(c);
+}
+
+nmf_status half_h(nmf_ctx* c) {
+  if (c->bf16) {
+    TRY_HIP(launch_gemm_nt_bf16(c->c2b, c->WbT, c->ppad, c->rp, c->VTb, c->ldvt, c->n, c->p,
+                                c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, c->st));
+  } else {
+    TRY_HIP(launch_gemm_tn(c->c2, c->Wp, c->rp, c->rp, c->Vk, c->ldvk, c->n, c->p, c->s2.splits,
+                           c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, c->st));
+  }
+  TRY_HIP(launch_update_h(c->rp, c->n, c->r, c->part2, c->s2.ldp, c->s2.sp, c->s2.splits, false,
+                          c->GW, c->Hp, c->npad, c->Huser, c->bf16 ? c->Hb : nullptr, c->bf16,
+                          c->st));
+  return gram_h(c);
+}
+
+nmf_status objective_async(nmf_ctx* c, const float* Wp) {
+  TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart, c->st));
+  TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, c->fdev, c->st));
+  return NMF_OK;
+}
+
+nmf_status read_f(nmf_ctx* c, double* f) {
+  TRY_HIP(hipMemcpyAsync(c->hostbuf, c->fdev, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  TRY_HIP(hipStreamSynchronize(c->st));
+  *f = c->hostbuf[0];
+  return NMF_OK;
+}
+
+void free_ctx(nmf_ctx* c) {
+  if (!c) return;
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->hostbuf) (void)hipHostFree(c->hostbuf);
+  delete c;
+}
+
+nmf_status setup(nmf_ctx* c) {
+  const int64_t p = c->p, n = c->n;
+  const int rp = c->rp;
+  c->ppad = round_up(p, 256);
+  c->npad = round_up(n, 256);
+  c->bf16 = (c->opt.precision == NMF_BF16);
+
+  // V as seen by the FP32 kernels: the caller's buffer when it is 16-byte
+  // aligned with a row stride that keeps rows aligned, else a padded copy.
+  const bool v_ok = (reinterpret_cast<uintptr_t>(c->Vuser) % 16 == 0) && (c->ldv % 4 == 0);
+  c->ldvk = v_ok ? c->ldv : round_up(n, 4);
+
+  // tiles and splits
+  const int64_t target = 1024;
+  if (!c->bf16) {
+    c->c1 = nt_config(rp, false);
+    c->cgh = nt_config(rp, true);
+    c->c2 = tn_config(rp, false);
+    c->cgw = tn_config(rp, true);
+    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, 32, target, 4);
+    c->s2 = plan_split(rp, n, p, c->c2.bm, c->c2.bn, 32, target, 4);
+    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 32, 256, 8);
+    c->sgw = plan_split(rp, rp, p, c->cgw.bm, c->cgw.bn, 32, 256, 8);
+  } else {
+    c->c1 = nt_config(rp, false);
+    c->cgh = nt_bf16_config(rp, true);
+    c->c2b = nt_bf16_config(rp, false);
+    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, 64, target, 4);
+    c->s2 = plan_split(rp, n, p, c->c2b.bm, c->c2b.bn, 64, target, 4);
+    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 64, 256, 8);
+    c->sgw = plan_split(rp, rp, p, c->cgh.bm, c->cgh.bn, 64, 256, 8);
+    c->ldvb = round_up(n, 8);
+    c->ldvt = round_up(p, 8);
+  }
+  c->nparts = objective_parts(p, n);
+
+  // carve one allocation, 256-byte aligned pieces
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t oVc = v_ok ? 0 : take(sizeof(float) * (size_t)p * c->ldvk);
+  const size_t oWp = take(sizeof(float) * (size_t)c->ppad * rp);
+  const size_t oHp = take(sizeof(float) * (size_t)rp * c->npad);
+  const size_t oGH = take(sizeof(float) * (size_t)rp * rp);
+  const size_t oGW = take(sizeof(float) * (size_t)rp * rp);
+  const size_t o1 = take(sizeof(float) * (size_t)c->s1.splits * c->s1.sp);
+  const size_t o2 = take(sizeof(float) * (size_t)c->s2.splits * c->s2.sp);
+  const size_t og = take(sizeof(float) * std::max((size_t)c->sgh.splits * c->sgh.sp,
+                                                  (size_t)c->sgw.splits * c->sgw.sp));
+  const size_t ofp = take(sizeof(double) * (size_t)c->nparts);
+  const size_t ofd = take(sizeof(double) * 2);
+  const size_t ofl = take(sizeof(uint32_t) * 4);
+  size_t oVb = 0, oVTb = 0, oHb = 0, oWbT = 0;
+  if (c->bf16) {
+    oVb = take(sizeof(uint16_t) * (size_t)p * c->ldvb);
+    oVTb = take(sizeof(uint16_t) * (size_t)n * c->ldvt);
+    oHb = take(sizeof(uint16_t) * (size_t)rp * c->npad);
+    oWbT = take(sizeof(uint16_t) * (size_t)rp * c->ppad);
+  }
+  if (hipMalloc(&c->ws, off) != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return NMF_ENOMEM;
+  }
+  char* base = static_cast<char*>(c->ws);
+  if (!v_ok) c->Vcopy = reinterpret_cast<float*>(base + oVc);
+  c->Wp = reinterpret_cast<float*>(base + oWp);
+  c->Hp = reinterpret_cast<float*>(base + oHp);
+  c->GH = reinterpret_cast<float*>(base + oGH);
+  c->GW = reinterpret_cast<float*>(base + oGW);
+  c->part1 = reinterpret_cast<float*>(base + o1);
+  c->part2 = reinterpret_cast<float*>(base + o2);
+  c->partg = reinterpret_cast<float*>(base + og);
+  c->fpart = reinterpret_cast<double*>(base + ofp);
+  c->fdev = reinterpret_cast<double*>(base + ofd);
+  c->flag = reinterpret_cast<uint32_t*>(base + ofl);
+  if (c->bf16) {
+    c->Vb = reinterpret_cast<uint16_t*>(base + oVb);
+    c->VTb = reinterpret_cast<uint16_t*>(base + oVTb);
+    c->Hb = reinterpret_cast<uint16_t*>(base + oHb);
+    c->WbT = reinterpret_cast<uint16_t*>(base + oWbT);
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->hostbuf), 2 * sizeof(double), 0) != hipSuccess) {
+    c->hostbuf = nullptr;
+    (void)hipGetLastError();
+    return NMF_ENOMEM;
+  }
+
+  // zero the whole workspace (padding must read as zero)
+  TRY_HIP(launch_fill_u32(static_cast<uint32_t*>(c->ws), (int64_t)(off / 4), 0u, c->st));
+
+  if (c->opt.validate) {
+    TRY_HIP(launch_validate(c->Vuser, c->ldv, p, n, c->flag, c->st));
+    TRY_HIP(hipMemcpyAsync(c->hostbuf, c->flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->st));
+    TRY_HIP(hipStreamSynchronize(c->st));
+    uint32_t bad;
+    std::memcpy(&bad, c->hostbuf, sizeof(bad));
+    if (bad) return NMF_EINVAL;
+  }
+
+  if (!v_ok) {
+    TRY_HIP(launch_copy_pad(c->Vuser, c->ldv, p, n, c->Vcopy, c->ldvk, c->st));
+    c->Vk = c->Vcopy;
+  } else {
+    c->Vk = c->Vuser;
+  }
+
+  if (c->opt.seed != 0) {
+    TRY_HIP(launch_uniform(c->Wuser, p, c->r, c->r, c->opt.seed, 0u, c->st));
+    TRY_HIP(launch_uniform(c->Huser, c->r, n, n, c->opt.seed, 1u, c->st));
+  }
+  TRY_HIP(launch_copy_pad(c->Wuser, c->r, p, c->r, c->Wp, rp, c->st));
+  TRY_HIP(launch_copy_pad(c->Huser, n, c->r, n, c->Hp, c->npad, c->st));
+
+  if (c->bf16) {
+    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->Vb, c->ldvb, false, c->st));
+    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->VTb, c->ldvt, true, c->st));
+    TRY_HIP(launch_cast_bf16(c->Hp, c->npad, rp, c->npad, c->Hb, c->npad, false, c->st));
+    TRY_HIP(launch_cast_bf16(c->Wp, rp, c->ppad, rp, c->WbT, c->ppad, true, c->st));
+  }
+
+  // ||V||_F^2 (objective with W = 0), then the Grams of the start
+  TRY(objective_async(c, nullptr));
+  TRY(read_f(c, &c->nv2));
+  TRY(gram_h(c));
+  TRY(gram_w(c));
+  return NMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nmf_default_options(nmf_options* opt) {
+  if (!opt) return;
+  opt->precision = NMF_FP32;
+  opt->tol_kind = NMF_TOL_REL_CHANGE;
+  opt->tol = 1e-9;
+  opt->check_every = 1;
+  opt->validate = 0;
+  opt->seed = 0;
+}
+
+nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n, int64_t ldv, int32_t r,
+                    float* W, float* H, const nmf_options* opt, void* stream) {
+  if (!out) return NMF_EINVAL;
+  *out = nullptr;
+  nmf_options o;
+  nmf_default_options(&o);
+  if (opt) o = *opt;
+  if (p <= 0 || n <= 0 || r <= 0 || ldv < n) return NMF_EINVAL;
+  TRY(check_ptr(V));
+  TRY(check_ptr(W));
+  TRY(check_ptr(H));
+  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol)) return NMF_EINVAL;
+  if (o.precision != NMF_FP32 && o.precision != NMF_BF16) return NMF_EUNSUPPORTED;
+  if (o.tol_kind != NMF_TOL_REL_CHANGE && o.tol_kind != NMF_TOL_GAP_NORMALIZED)
+    return NMF_EUNSUPPORTED;
+  if (r > NMF_MAX_RANK || p > kMaxDim || n > kMaxDim) return NMF_EUNSUPPORTED;
+
+  nmf_ctx* c = new (std::nothrow) nmf_ctx();
+  if (!c) return NMF_ENOMEM;
+  c->st = static_cast<hipStream_t>(stream);
+  c->p = p;
+  c->n = n;
+  c->ldv = ldv;
+  c->r = r;
+  c->rp = padded_rank(r);
+  c->opt = o;
+  c->Vuser = V;
+  c->Wuser = W;
+  c->Huser = H;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    free_ctx(c);
+    return NMF_EDEVICE;
+  }
+  nmf_status s = setup(c);
+  if (s != NMF_OK) {
+    (void)hipStreamSynchronize(c->st);
+    free_ctx(c);
+    return s;
+  }
+  *out = c;
+  return NMF_OK;
+}
+
+nmf_status nmf_update_w(nmf_ctx* c) {
+  if (!c) return NMF_EINVAL;
+  return half_w(c);
+}
+
+nmf_status nmf_update_h(nmf_ctx* c) {
+  if (!c) return NMF_EINVAL;
+  return half_h(c);
+}
+
+nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
+  if (!c || iters < 0) return NMF_EINVAL;
+  for (int32_t it = 0; it < iters; ++it) {
+    TRY(half_w(c));
+    TRY(half_h(c));
+  }
+  return NMF_OK;
+}
+
+nmf_status nmf_objective(nmf_ctx* c, double* f_host) {
+  if (!c || !f_host) return NMF_EINVAL;
+  TRY(objective_async(c, c->Wp));
+  double f;
+  TRY(read_f(c, &f));
+  *f_host = f;
+  return std::isfinite(f) ? NMF_OK : NMF_ENONFINITE;
+}
+
+nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double* f_host,
+                     double* trace, int32_t trace_len) {
+  if (!c || max_iters < 0 || !iters_done || !f_host) return NMF_EINVAL;
+  if (trace && trace_len < 0) return NMF_EINVAL;
+  double f_prev;
+  *iters_done = 0;
+  nmf_status s = nmf_objective(c, &f_prev);
+  *f_host = f_prev;
+  if (s != NMF_OK) return s;
+  int32_t nt = 0;
+  if (trace && nt < trace_len) trace[nt++] = f_prev;
+  int32_t k = 0;
+  while (k < max_iters) {
+    const int32_t todo = std::min(c->opt.check_every, max_iters - k);
+    TRY(nmf_step(c, todo));
+    k += todo;
+    double f;
+    s = nmf_objective(c, &f);
+    *iters_done = k;
+    *f_host = f;
+    if (s != NMF_OK) return s;
+    if (trace && nt < trace_len) trace[nt++] = f;
+    bool done;
+    if (c->opt.tol_kind == NMF_TOL_REL_CHANGE)
+      done = std::fabs(f - f_prev) / (std::fabs(f_prev) + 1.0) < c->opt.tol;
+    else
+      done = (c->nv2 > 0.0 ? f / c->nv2 : 0.0) <= c->opt.tol;
+    f_prev = f;
+    if (done) return NMF_OK;
+  }
+  return NMF_ENOTCONVERGED;
+}
+
+void nmf_destroy(nmf_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  free_ctx(c);
+}
+
+const char* nmf_strerror(nmf_status s) {
+  switch (s) {
+    case NMF_OK: return "success";
+    case NMF_ENOTCONVERGED: return "iteration cap reached before the stopping rule held";
+    case NMF_EINVAL: return "invalid argument or invalid data";
+    case NMF_ENOMEM: return "device allocation failed";
+    case NMF_EDEVICE: return "HIP runtime error";
+    case NMF_ENONFINITE: return "objective is not finite";
+    case NMF_EUNSUPPORTED: return "unsupported rank, size or option";
+  }
+  return "unknown status";
+}
+
+int32_t nmf_version(void) { return 100; }
+
+}  // extern "C"

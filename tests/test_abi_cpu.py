@@ -1,0 +1,116 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+that include/nmf.h declares, and rejects bad arguments before any device
+work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1003_3272_amd import nmf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(nmf_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = _declared_functions()
+    for required in ("nmf_init", "nmf_step", "nmf_objective", "nmf_solve", "nmf_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nmf.load()
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_options_struct_layout_matches_header():
+    # int32, int32, double, int32, int32, uint64 -> 32 bytes, double at 8
+    assert ctypes.sizeof(nmf.NmfOptions) == 32
+    assert nmf.NmfOptions.tol.offset == 8
+    assert nmf.NmfOptions.seed.offset == 24
+
+
+def test_default_options():
+    o = nmf.NmfOptions()
+    nmf.load().nmf_default_options(ctypes.byref(o))
+    assert (o.precision, o.tol_kind, o.tol, o.check_every, o.validate, o.seed) == \
+        (0, 0, 1e-9, 1, 0, 0)
+
+
+def test_strerror_and_version():
+    lib = nmf.load()
+    for s in (0, 1, -1, -2, -3, -4, -5):
+        assert len(nmf.strerror(s)) > 0
+    assert nmf.strerror(99) == "unknown status"
+    assert lib.nmf_version() >= 100
+
+
+FAKE = 0x10000  # aligned, never dereferenced: checks reject before device work
+
+
+def _init(V=FAKE, p=8, n=8, ldv=8, r=2, W=FAKE, H=FAKE, opt=None, out=True):
+    lib = nmf.load()
+    ctx = ctypes.c_void_p(123)
+    o = opt if opt is not None else nmf.options()
+    st = lib.nmf_init(ctypes.byref(ctx) if out else None, V, p, n, ldv, r, W, H,
+                      ctypes.byref(o), None)
+    return st, ctx
+
+
+@pytest.mark.parametrize("kw", [
+    dict(V=None), dict(W=None), dict(H=None), dict(p=0), dict(n=0), dict(r=0),
+    dict(p=-3), dict(ldv=7), dict(V=FAKE + 2), dict(W=FAKE + 1), dict(H=FAKE + 3),
+])
+def test_init_rejects_bad_arguments(kw):
+    st, ctx = _init(**kw)
+    assert st == nmf.NMF_EINVAL
+    assert ctx.value is None
+
+
+def test_init_rejects_null_out():
+    st, _ = _init(out=False)
+    assert st == nmf.NMF_EINVAL
+
+
+def test_init_rejects_rank_above_max():
+    st, _ = _init(r=nmf.MAX_RANK + 1)
+    assert st == nmf.NMF_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("check_every", 0, nmf.NMF_EINVAL),
+    ("tol", float("nan"), nmf.NMF_EINVAL),
+    ("tol", -1.0, nmf.NMF_EINVAL),
+    ("tol", float("inf"), nmf.NMF_EINVAL),
+    ("precision", 7, nmf.NMF_EUNSUPPORTED),
+    ("tol_kind", 5, nmf.NMF_EUNSUPPORTED),
+])
+def test_init_rejects_bad_options(field, value, code):
+    o = nmf.options()
+    setattr(o, field, value)
+    st, _ = _init(opt=o)
+    assert st == code
+
+
+def test_null_context_calls():
+    lib = nmf.load()
+    f = ctypes.c_double()
+    it = ctypes.c_int32()
+    assert lib.nmf_step(None, 1) == nmf.NMF_EINVAL
+    assert lib.nmf_update_w(None) == nmf.NMF_EINVAL
+    assert lib.nmf_update_h(None) == nmf.NMF_EINVAL
+    assert lib.nmf_objective(None, ctypes.byref(f)) == nmf.NMF_EINVAL
+    assert lib.nmf_solve(None, 1, ctypes.byref(it), ctypes.byref(f), None, 0) == nmf.NMF_EINVAL
+    lib.nmf_destroy(None)  # must not crash

@@ -282,3 +282,20 @@ def test_bf16_path_close_to_fp64():
     a = o.update_w(V, W0, H0, bf16=True)
     b = o.update_w(V, W0, H0)
     assert np.max(np.abs(a - b) / b) < 2 * 2 ** -8
+
+
+def test_rel_change_statistic_values():
+    """|f_n - f_{n-1}| / (|f_{n-1}| + 1): the +1 keeps it finite at f = 0."""
+    assert o.rel_change(3.0, 1.0) == 1.0
+    assert o.rel_change(0.5, 0.0) == 0.5
+    assert o.rel_change(1.0, 3.0) == 0.5
+
+
+def test_rel_change_stop_agrees_with_plain_run():
+    V, W0, H0 = g.small_uniform()
+    _, _, tr = o.run(V, W0, H0, 80)
+    stat = np.abs(np.diff(tr)) / (np.abs(tr[:-1]) + 1.0)
+    tol = float(stat[50]) * 1.0000001
+    first = int(np.argmax(stat < tol)) + 1
+    _, _, k, f, _ = o.solve(V, W0, H0, 200, tol=tol)
+    assert k == first and f == tr[first]
