@@ -128,6 +128,28 @@ nmf_status nmf_objective(nmf_ctx* ctx, double* f_host);
 nmf_status nmf_solve(nmf_ctx* ctx, int32_t max_iters, int32_t* iters_done_host,
                      double* f_host, double* trace_host, int32_t trace_len);
 
+/* Stages of one iteration, as timed by the profiler below. */
+typedef enum {
+  NMF_STAGE_GEMM_VHT = 0,   /* V H^T split-K partials (W numerator)          */
+  NMF_STAGE_UPDATE_W = 1,   /* partial sum + W (H H^T) + ratio update of W    */
+  NMF_STAGE_GRAM_W = 2,     /* W^T W                                          */
+  NMF_STAGE_GEMM_WTV = 3,   /* W^T V split-K partials (H numerator)           */
+  NMF_STAGE_UPDATE_H = 4,   /* partial sum + (W^T W) H + ratio update of H    */
+  NMF_STAGE_GRAM_H = 5,     /* H H^T                                          */
+  NMF_STAGE_OBJECTIVE = 6,  /* float64 objective and its reduction            */
+  NMF_STAGE_COUNT = 7
+} nmf_stage;
+
+/* Start timing: every stage enqueued afterwards (up to max_records stages)
+   is bracketed by a pair of HIP events on the context's stream.  Restarts
+   discard earlier records.  Returns NMF_EINVAL for max_records < 1. */
+nmf_status nmf_profile_start(nmf_ctx* ctx, int32_t max_records);
+
+/* Stop timing, synchronize the stream and write, per nmf_stage, the summed
+   event time in milliseconds (ms_host[NMF_STAGE_COUNT]) and the number of
+   timed launches (launches_host[NMF_STAGE_COUNT]); either may be NULL. */
+nmf_status nmf_profile_stop(nmf_ctx* ctx, double* ms_host, int32_t* launches_host);
+
 /* Release the context's workspace.  NULL is ignored. */
 void nmf_destroy(nmf_ctx* ctx);
 

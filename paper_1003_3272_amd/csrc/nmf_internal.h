@@ -33,6 +33,16 @@ struct TnCfg {
   int threads;
 };
 
+// Gram reduction carried by a product kernel (see gram_reduce_slice):
+// G[e] = sum_{q < count} part[q * elems + e] for e < elems.  part == nullptr
+// disables it.
+struct GramRed {
+  const float* part;
+  int count;
+  int elems;
+  float* G;
+};
+
 NtCfg nt_config(int rp, bool gram);
 TnCfg tn_config(int rp, bool gram);
 NtCfg nt_bf16_config(int rp, bool gram);
@@ -43,18 +53,20 @@ NtCfg nt_bf16_config(int rp, bool gram);
 hipError_t launch_gemm_nt(const NtCfg& cfg, const float* X, int64_t ldx,
                           int64_t M, const float* Y, int64_t ldy, int64_t N,
                           int64_t K, int splits, int64_t kchunk, float* part,
-                          int64_t ldp, int64_t sp, hipStream_t st);
+                          int64_t ldp, int64_t sp, const GramRed& gr,
+                          hipStream_t st);
 hipError_t launch_gemm_tn(const TnCfg& cfg, const float* A, int64_t lda,
                           int64_t M, const float* B, int64_t ldb, int64_t N,
                           int64_t K, int splits, int64_t kchunk, float* part,
-                          int64_t ldp, int64_t sp, hipStream_t st);
+                          int64_t ldp, int64_t sp, const GramRed& gr,
+                          hipStream_t st);
 
 // ---- BF16 NT product (16x16x32 MFMA, FP32 accumulation) ------------------
 hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X,
                                int64_t ldx, int64_t M, const uint16_t* Y,
                                int64_t ldy, int64_t N, int64_t K, int splits,
                                int64_t kchunk, float* part, int64_t ldp,
-                               int64_t sp, hipStream_t st);
+                               int64_t sp, const GramRed& gr, hipStream_t st);
 
 // G[m][c] = sum_s part[s][m][c] for m, c < rp; written with pitch rp.
 // With bf16 != nullptr also writes the bfloat16 rounding of G there.
@@ -62,22 +74,29 @@ hipError_t launch_reduce_gram(const float* part, int64_t ldp, int64_t sp,
                               int splits, int rp, float* G, uint16_t* Gbf,
                               hipStream_t st);
 
+// Number of workgroups of the update kernels (grid-stride; capped at cap).
+int update_grid(int rp, int64_t p, int cap);
+int update_h_grid(int64_t n, int cap);
+
 // W half-step epilogue.  Wp (ppad x rp) holds the current W; A partials are
 // part[s][i][k] (pitch ldp, split pitch sp).  Writes the new W to Wp, to the
 // caller's W (p x r) and, for the BF16 tier, to WbT (rp x ldwt, transposed).
+// gout != nullptr (rp <= 64): also writes per-workgroup Grams of the new W
+// (grid x rp x rp).  gram_only: no update, Grams of the current W only.
 hipError_t launch_update_w(int rp, int64_t p, int r, const float* part,
                            int64_t ldp, int64_t sp, int splits, const float* G,
                            float* Wp, float* Wcaller, uint16_t* WbT,
-                           int64_t ldwt, bool bf16, hipStream_t st);
+                           int64_t ldwt, bool bf16, float* gout, int grid,
+                           bool gram_only, hipStream_t st);
 
-// H half-step epilogue.  Hp (rp x ldh) holds the current H.  S partials are
-// part[s][k][j] (transposed == false) or part[s][j][k] (transposed == true).
-// Writes Hp, the caller's H (r x n) and, for the BF16 tier, Hb (rp x ldh).
+// H half-step epilogue.  Hp (rp x ldh) holds the current H; S partials are
+// part[s][k][j].  Writes Hp, the caller's H (r x n) and, for the BF16 tier,
+// Hb (rp x ldh); gout/gram_only as for the W update (Grams of H H^T).
 hipError_t launch_update_h(int rp, int64_t n, int r, const float* part,
-                           int64_t ldp, int64_t sp, int splits,
-                           bool transposed, const float* G, float* Hp,
-                           int64_t ldh, float* Hcaller, uint16_t* Hb,
-                           bool bf16, hipStream_t st);
+                           int64_t ldp, int64_t sp, int splits, const float* G,
+                           float* Hp, int64_t ldh, float* Hcaller, uint16_t* Hb,
+                           bool bf16, float* gout, int grid, bool gram_only,
+                           hipStream_t st);
 
 // Objective partials: one double per 64 x 64 tile of V - W H.
 hipError_t launch_objective(int rp, const float* V, int64_t ldv, int64_t p,

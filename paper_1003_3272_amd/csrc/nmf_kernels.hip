@@ -75,6 +75,31 @@ __device__ __forceinline__ uint4 load8h(const uint16_t* __restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
+// Distributed Gram reduction carried by a product kernel: G[e] = sum_q
+// part[q][e] over the `count` per-workgroup Gram partials written by the
+// previous update kernel.  Workgroups take elements round-robin; 32 lanes
+// share an element, each summing partials q = lane, lane + 32, ... in order,
+// then a fixed xor butterfly combines the 32 lane sums (commutative at each
+// level, so every lane holds the same bits).  The result does not depend on
+// the product's grid.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void gram_reduce_slice(const GramRed& g) {
+  if (!g.part) return;
+  const int64_t nwg = (int64_t)gridDim.x * gridDim.y * gridDim.z;
+  const int64_t b = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  const int groups = blockDim.x >> 5, grp = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+  for (int64_t e0 = b * groups; e0 < g.elems; e0 += nwg * groups) {
+    const int64_t e = e0 + grp;
+    float s = 0.f;
+    if (e < g.elems)
+      for (int q = l32; q < g.count; q += 32) s += g.part[(int64_t)q * g.elems + e];
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+    if (e < g.elems && l32 == 0) g.G[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // NT product, FP32:  part[s][m][c] = sum_{k in split s} X[m][k] * Y[c][k].
 // Workgroup tile BM x BN, BK = 32 reduction slots per LDS stage, WM x WN
 // waves each owning (16 MB) x (16 NB) outputs.  Each lane reads 4
@@ -86,7 +111,7 @@ template <int MB, int NB, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(
     const float* __restrict__ X, int64_t ldx, int64_t M,
     const float* __restrict__ Y, int64_t ldy, int64_t N, int64_t K,
-    int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp) {
+    int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
   constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, BK = 32, PITCH = BK + 4;
   constexpr int T = 64 * WM * WN;
   constexpr int XQ = BM * (BK / 4), YQ = BN * (BK / 4);
@@ -101,6 +126,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(
   const int64_t m0 = (int64_t)blockIdx.y * BM;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (K < kb + kchunk) ? K : kb + kchunk;
+  gram_reduce_slice(gr);
 
   v4f acc[MB][NB];
 #pragma unroll
@@ -184,7 +210,7 @@ template <int MB, int NB, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt_bf16(
     const uint16_t* __restrict__ X, int64_t ldx, int64_t M,
     const uint16_t* __restrict__ Y, int64_t ldy, int64_t N, int64_t K,
-    int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp) {
+    int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
   constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, BK = 64, PITCH = BK + 8;
   constexpr int T = 64 * WM * WN;
   constexpr int XQ = BM * (BK / 8), YQ = BN * (BK / 8);
@@ -199,6 +225,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt_bf16(
   const int64_t m0 = (int64_t)blockIdx.y * BM;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (K < kb + kchunk) ? K : kb + kchunk;
+  gram_reduce_slice(gr);
 
   v4f acc[MB][NB];
 #pragma unroll
@@ -313,7 +340,7 @@ template <int MB, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(
     const float* __restrict__ A, int64_t lda, int64_t M,
     const float* __restrict__ B, int64_t ldb, int64_t N, int64_t K,
-    int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp) {
+    int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
   constexpr int NB = 4;
   constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, BK = 32;
   constexpr int PA = BM + 4, PB = BN + 4;
@@ -330,6 +357,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(
   const int64_t m0 = (int64_t)blockIdx.y * BM;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (K < kb + kchunk) ? K : kb + kchunk;
+  gram_reduce_slice(gr);
 
   v4f acc[MB][NB];
 #pragma unroll
@@ -399,18 +427,46 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(
 }
 
 // ---------------------------------------------------------------------------
-// Gram reduction: G[m][c] = sum_s part[s][m][c], s ascending.
+// Split-K sums.  The partial tiles are summed in ascending split order; the
+// loads of 8 splits are issued together before the (ordered) adds so the
+// loop is not a chain of dependent memory round trips.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 sum_splits4(const float* __restrict__ part, int64_t off,
+                                              int64_t sp, int splits) {
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  int q = 0;
+  for (; q + 8 <= splits; q += 8) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const float4*>(part + (q + u) * sp + off);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s.x += v[u].x; s.y += v[u].y; s.z += v[u].z; s.w += v[u].w;
+    }
+  }
+  for (; q < splits; ++q) {
+    const float4 v = *reinterpret_cast<const float4*>(part + q * sp + off);
+    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+  }
+  return s;
+}
+
+// Gram reduction: G[m][c] = sum_s part[s][m][c], s ascending; 4 columns per
+// thread (rp is a multiple of 16, the partial pitch a multiple of 4).
 __global__ void k_reduce_gram(const float* __restrict__ part, int64_t ldp,
                               int64_t sp, int splits, int rp,
                               float* __restrict__ G, uint16_t* __restrict__ Gbf) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)rp * rp) return;
-  const int64_t m = idx / rp, cc = idx % rp;
-  float s = 0.f;
-  for (int q = 0; q < splits; ++q) s += part[q * sp + m * ldp + cc];
-  G[idx] = s;
-  if (Gbf) Gbf[idx] = to_bf16(s);
+  if (idx >= (int64_t)rp * rp / 4) return;
+  const int64_t m = idx / (rp / 4), cc = 4 * (idx % (rp / 4));
+  const float4 s = sum_splits4(part, m * ldp + cc, sp, splits);
+  *reinterpret_cast<float4*>(&G[m * rp + cc]) = s;
+  if (Gbf) {
+    Gbf[m * rp + cc + 0] = to_bf16(s.x);
+    Gbf[m * rp + cc + 1] = to_bf16(s.y);
+    Gbf[m * rp + cc + 2] = to_bf16(s.z);
+    Gbf[m * rp + cc + 3] = to_bf16(s.w);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -418,51 +474,125 @@ __global__ void k_reduce_gram(const float* __restrict__ part, int64_t ldp,
 //   a_ik = sum_s part[s][i][k]                 (numerator (V H^T)_ik)
 //   b_ik = sum_l w_il G_lk                     (denominator (W (H H^T))_ik)
 //   w_ik <- w_ik * (a_ik / b_ik)  if b_ik > 0, else unchanged.
-// A workgroup owns ROWS rows of W and all RP ranks; it snapshots its rows in
-// LDS (rounded to bf16 in the BF16 tier, where the product takes bf16
-// operands) and streams G through LDS in chunks of KC columns.
+// A workgroup takes ROWS rows of W at a time (grid-stride) with all RP
+// ranks; it snapshots the rows in LDS (rounded to bf16 in the BF16 tier,
+// where the product takes bf16 operands) and streams G through LDS in chunks
+// of KC columns.  Each thread produces 4 adjacent ranks of one row per chunk
+// (ROWS * KC / 4 == 256).
+// With gout != nullptr (RP <= 64) the workgroup also accumulates the Gram
+// W_new^T W_new of the rows it updated (bf16-rounded in the BF16 tier) and
+// writes it to gout[blockIdx.x]; the next product kernel reduces these.
+// gram_only skips the update and only forms the Gram of the current W.
 // ---------------------------------------------------------------------------
 template <int RP>
 __global__ __launch_bounds__(256) void k_update_w(
     int64_t p, int r, const float* __restrict__ part, int64_t ldp, int64_t sp,
     int splits, const float* __restrict__ G, float* __restrict__ Wp,
     float* __restrict__ Wc, uint16_t* __restrict__ WbT, int64_t ldwt,
-    int bf16) {
-  constexpr int ROWS = 32, KC = RP < 64 ? RP : 64;
-  __shared__ float Ws[ROWS * RP];
-  __shared__ float Gs[RP * KC];
+    int bf16, float* __restrict__ gout, int gram_only) {
+  constexpr int KC = RP < 64 ? RP : 64;
+  constexpr int ROWS = 1024 / KC;
+  constexpr bool FUSE = RP <= 64;         // Gram partial fits one thread tile
+  constexpr int TB = RP / 16;             // Gram tile per thread: TB x TB
+  __shared__ __attribute__((aligned(16))) float Ws[ROWS * RP];
+  __shared__ __attribute__((aligned(16))) float Gs[RP * KC];
+  __shared__ __attribute__((aligned(16))) float Wn[FUSE ? ROWS * RP : 4];
   const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+  const int i = tid / (KC / 4), k4 = 4 * (tid % (KC / 4));
+  const bool gram = FUSE && gout != nullptr;
+  const int gk = (tid / 16) * TB, gl = (tid % 16) * TB;
+  float ga[TB][TB];
+#pragma unroll
+  for (int a = 0; a < TB; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) ga[a][b] = 0.f;
 
-  for (int idx = tid; idx < ROWS * RP; idx += 256) {
-    const int i = idx / RP, l = idx % RP;
-    float w = (i0 + i < p) ? Wp[(i0 + i) * RP + l] : 0.f;
-    Ws[idx] = bf16 ? bf16_val(w) : w;
-  }
-  for (int kc0 = 0; kc0 < RP; kc0 += KC) {
+  for (int64_t blk = blockIdx.x; blk * ROWS < p; blk += gridDim.x) {
+    const int64_t i0 = blk * ROWS;
+    const int64_t row = i0 + i;
     __syncthreads();
-    for (int idx = tid; idx < RP * KC; idx += 256) {
-      const int l = idx / KC, kk = idx % KC;
-      const float gv = G[l * RP + kc0 + kk];
-      Gs[idx] = bf16 ? bf16_val(gv) : gv;
+    for (int idx = tid; idx < ROWS * RP / 4; idx += 256) {
+      const int ii = idx / (RP / 4), l4 = 4 * (idx % (RP / 4));
+      float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (i0 + ii < p) w = *reinterpret_cast<const float4*>(&Wp[(i0 + ii) * RP + l4]);
+      if (bf16) {
+        w.x = bf16_val(w.x); w.y = bf16_val(w.y); w.z = bf16_val(w.z); w.w = bf16_val(w.w);
+      }
+      *reinterpret_cast<float4*>(&Ws[ii * RP + l4]) = w;
+      if (FUSE && gram_only) *reinterpret_cast<float4*>(&Wn[ii * RP + l4]) = w;
     }
-    __syncthreads();
-    for (int idx = tid; idx < ROWS * KC; idx += 256) {
-      const int i = idx / KC, kk = idx % KC;
-      const int64_t row = i0 + i;
-      if (row >= p) continue;
-      const int k = kc0 + kk;
-      float b = 0.f;
+    if (!gram_only) {
+      for (int kc0 = 0; kc0 < RP; kc0 += KC) {
+        if (!FUSE || kc0 > 0 || blk == blockIdx.x) {  // G chunk (once when RP <= 64)
+          __syncthreads();
+          for (int idx = tid; idx < RP * KC / 4; idx += 256) {
+            const int l = idx / (KC / 4), kk = 4 * (idx % (KC / 4));
+            float4 gv = *reinterpret_cast<const float4*>(&G[l * RP + kc0 + kk]);
+            if (bf16) {
+              gv.x = bf16_val(gv.x); gv.y = bf16_val(gv.y); gv.z = bf16_val(gv.z); gv.w = bf16_val(gv.w);
+            }
+            *reinterpret_cast<float4*>(&Gs[l * KC + kk]) = gv;
+          }
+        }
+        __syncthreads();
+        const int k = kc0 + k4;
+        float4 wn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < p) {
+          const float4 a = sum_splits4(part, row * ldp + k, sp, splits);
+          float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
 #pragma unroll 8
-      for (int l = 0; l < RP; ++l) b = fmaf(Ws[i * RP + l], Gs[l * KC + kk], b);
-      float a = 0.f;
-      for (int q = 0; q < splits; ++q) a += part[q * sp + row * ldp + k];
-      const float w = Wp[row * RP + k];
-      const float wn = (b > 0.f) ? w * (a / b) : w;
-      Wp[row * RP + k] = wn;
-      if (k < r) Wc[row * r + k] = wn;
-      if (WbT) WbT[(int64_t)k * ldwt + row] = to_bf16(wn);
+          for (int l = 0; l < RP; ++l) {
+            const float wl = Ws[i * RP + l];
+            const float4 g4 = *reinterpret_cast<const float4*>(&Gs[l * KC + k4]);
+            b0 = fmaf(wl, g4.x, b0);
+            b1 = fmaf(wl, g4.y, b1);
+            b2 = fmaf(wl, g4.z, b2);
+            b3 = fmaf(wl, g4.w, b3);
+          }
+          const float4 w = *reinterpret_cast<const float4*>(&Wp[row * RP + k]);
+          wn.x = (b0 > 0.f) ? w.x * (a.x / b0) : w.x;
+          wn.y = (b1 > 0.f) ? w.y * (a.y / b1) : w.y;
+          wn.z = (b2 > 0.f) ? w.z * (a.z / b2) : w.z;
+          wn.w = (b3 > 0.f) ? w.w * (a.w / b3) : w.w;
+          *reinterpret_cast<float4*>(&Wp[row * RP + k]) = wn;
+          const float wv[4] = {wn.x, wn.y, wn.z, wn.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (k + e < r) Wc[row * r + k + e] = wv[e];
+            if (WbT) WbT[(int64_t)(k + e) * ldwt + row] = to_bf16(wv[e]);
+          }
+        }
+        if (FUSE) {
+          if (bf16) {
+            wn.x = bf16_val(wn.x); wn.y = bf16_val(wn.y); wn.z = bf16_val(wn.z); wn.w = bf16_val(wn.w);
+          }
+          *reinterpret_cast<float4*>(&Wn[i * RP + k]) = wn;
+        }
+      }
     }
+    if (gram) {
+      __syncthreads();
+#pragma unroll 4
+      for (int ii = 0; ii < ROWS; ++ii) {
+        float x[TB], y[TB];
+#pragma unroll
+        for (int a = 0; a < TB; ++a) {
+          x[a] = Wn[ii * RP + gk + a];
+          y[a] = Wn[ii * RP + gl + a];
+        }
+#pragma unroll
+        for (int a = 0; a < TB; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) ga[a][b] = fmaf(x[a], y[b], ga[a][b]);
+      }
+    }
+  }
+  if (gram) {
+    float* out = gout + (int64_t)blockIdx.x * RP * RP;
+#pragma unroll
+    for (int a = 0; a < TB; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) out[(gk + a) * RP + gl + b] = ga[a][b];
   }
 }
 
@@ -471,47 +601,130 @@ __global__ __launch_bounds__(256) void k_update_w(
 //   s_kj = sum_s part[s][k][j]                 (numerator (W^T V)_kj)
 //   d_kj = sum_l G_kl h_lj                     (denominator ((W^T W) H)_kj)
 //   h_kj <- h_kj * (s_kj / d_kj)  if d_kj > 0, else unchanged.
-// A workgroup owns COLS columns of H and all RP ranks.
+// A workgroup takes COLS = 64 columns of H at a time (grid-stride) with all
+// RP ranks; each thread produces 4 adjacent columns of one rank at a time.
+// With gout != nullptr (RP <= 64) it also accumulates the Gram H_new H_new^T
+// of its columns into gout[blockIdx.x]; gram_only skips the update.
 // ---------------------------------------------------------------------------
 template <int RP>
 __global__ __launch_bounds__(256) void k_update_h(
     int64_t n, int r, const float* __restrict__ part, int64_t ldp, int64_t sp,
     int splits, const float* __restrict__ G, float* __restrict__ Hp,
-    int64_t ldh, float* __restrict__ Hc, uint16_t* __restrict__ Hb, int bf16) {
+    int64_t ldh, float* __restrict__ Hc, uint16_t* __restrict__ Hb, int bf16,
+    float* __restrict__ gout, int gram_only) {
   constexpr int COLS = 64, KC = RP < 64 ? RP : 64;
-  __shared__ float Hs[RP * COLS];
-  __shared__ float Gs[KC * RP];
+  constexpr bool FUSE = RP <= 64;
+  constexpr int TB = RP / 16;
+  __shared__ __attribute__((aligned(16))) float Hs[RP * COLS];
+  __shared__ __attribute__((aligned(16))) float Gs[KC * RP];
+  constexpr int HP = RP + 1;  // padded pitch: conflict-free column writes
+  __shared__ float HnT[FUSE ? COLS * HP : 4];  // [j][k]
   const int tid = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * COLS;
+  const bool gram = FUSE && gout != nullptr;
+  const int gk = (tid / 16) * TB, gl = (tid % 16) * TB;
+  float ga[TB][TB];
+#pragma unroll
+  for (int a = 0; a < TB; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) ga[a][b] = 0.f;
 
-  for (int idx = tid; idx < RP * COLS; idx += 256) {
-    const int l = idx / COLS, jj = idx % COLS;
-    const float h = Hp[(int64_t)l * ldh + j0 + jj];
-    Hs[idx] = bf16 ? bf16_val(h) : h;
-  }
-  for (int kc0 = 0; kc0 < RP; kc0 += KC) {
+  for (int64_t blk = blockIdx.x; blk * COLS < n; blk += gridDim.x) {
+    const int64_t j0 = blk * COLS;
     __syncthreads();
-    for (int idx = tid; idx < KC * RP; idx += 256) {
-      const float gv = G[(int64_t)kc0 * RP + idx];
-      Gs[idx] = bf16 ? bf16_val(gv) : gv;
+    for (int idx = tid; idx < RP * COLS / 4; idx += 256) {
+      const int l = idx / (COLS / 4), jj = 4 * (idx % (COLS / 4));
+      float4 h = *reinterpret_cast<const float4*>(&Hp[(int64_t)l * ldh + j0 + jj]);
+      if (bf16) {
+        h.x = bf16_val(h.x); h.y = bf16_val(h.y); h.z = bf16_val(h.z); h.w = bf16_val(h.w);
+      }
+      *reinterpret_cast<float4*>(&Hs[l * COLS + jj]) = h;
+      if (FUSE && gram_only) {
+        HnT[(jj + 0) * HP + l] = h.x;
+        HnT[(jj + 1) * HP + l] = h.y;
+        HnT[(jj + 2) * HP + l] = h.z;
+        HnT[(jj + 3) * HP + l] = h.w;
+      }
     }
-    __syncthreads();
-    for (int idx = tid; idx < KC * COLS; idx += 256) {
-      const int kk = idx / COLS, jj = idx % COLS;
-      const int64_t j = j0 + jj;
-      if (j >= n) continue;
-      const int k = kc0 + kk;
-      float d = 0.f;
+    if (!gram_only) {
+      for (int kc0 = 0; kc0 < RP; kc0 += KC) {
+        if (!FUSE || kc0 > 0 || blk == blockIdx.x) {
+          __syncthreads();
+          for (int idx = tid; idx < KC * RP / 4; idx += 256) {
+            float4 gv = *reinterpret_cast<const float4*>(&G[(int64_t)kc0 * RP + 4 * idx]);
+            if (bf16) {
+              gv.x = bf16_val(gv.x); gv.y = bf16_val(gv.y); gv.z = bf16_val(gv.z); gv.w = bf16_val(gv.w);
+            }
+            *reinterpret_cast<float4*>(&Gs[4 * idx]) = gv;
+          }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < KC * COLS / 4; idx += 256) {
+          const int kk = idx / (COLS / 4), j4 = 4 * (idx % (COLS / 4));
+          const int64_t j = j0 + j4;
+          const int k = kc0 + kk;
+          float4 hn = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (j < n) {
+            float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
 #pragma unroll 8
-      for (int l = 0; l < RP; ++l) d = fmaf(Gs[kk * RP + l], Hs[l * COLS + jj], d);
-      float s = 0.f;
-      for (int q = 0; q < splits; ++q) s += part[q * sp + (int64_t)k * ldp + j];
-      const float h = Hp[(int64_t)k * ldh + j];
-      const float hn = (d > 0.f) ? h * (s / d) : h;
-      Hp[(int64_t)k * ldh + j] = hn;
-      if (k < r) Hc[(int64_t)k * n + j] = hn;
-      if (Hb) Hb[(int64_t)k * ldh + j] = to_bf16(hn);
+            for (int l = 0; l < RP; ++l) {
+              const float gl_ = Gs[kk * RP + l];
+              const float4 h4 = *reinterpret_cast<const float4*>(&Hs[l * COLS + j4]);
+              d0 = fmaf(gl_, h4.x, d0);
+              d1 = fmaf(gl_, h4.y, d1);
+              d2 = fmaf(gl_, h4.z, d2);
+              d3 = fmaf(gl_, h4.w, d3);
+            }
+            const float4 sv = sum_splits4(part, (int64_t)k * ldp + j, sp, splits);
+            const float4 h = *reinterpret_cast<const float4*>(&Hp[(int64_t)k * ldh + j]);
+            hn.x = (d0 > 0.f) ? h.x * (sv.x / d0) : h.x;
+            hn.y = (d1 > 0.f) ? h.y * (sv.y / d1) : h.y;
+            hn.z = (d2 > 0.f) ? h.z * (sv.z / d2) : h.z;
+            hn.w = (d3 > 0.f) ? h.w * (sv.w / d3) : h.w;
+            *reinterpret_cast<float4*>(&Hp[(int64_t)k * ldh + j]) = hn;
+            const float hv[4] = {hn.x, hn.y, hn.z, hn.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              if (j + e < n) {
+                if (k < r) Hc[(int64_t)k * n + j + e] = hv[e];
+                if (Hb) Hb[(int64_t)k * ldh + j + e] = to_bf16(hv[e]);
+              }
+            }
+          }
+          if (FUSE) {
+            if (bf16) {
+              hn.x = bf16_val(hn.x); hn.y = bf16_val(hn.y); hn.z = bf16_val(hn.z); hn.w = bf16_val(hn.w);
+            }
+            HnT[(j4 + 0) * HP + k] = hn.x;
+            HnT[(j4 + 1) * HP + k] = hn.y;
+            HnT[(j4 + 2) * HP + k] = hn.z;
+            HnT[(j4 + 3) * HP + k] = hn.w;
+          }
+        }
+      }
     }
+    if (gram) {
+      __syncthreads();
+#pragma unroll 4
+      for (int jj = 0; jj < COLS; ++jj) {
+        float x[TB], y[TB];
+#pragma unroll
+        for (int a = 0; a < TB; ++a) {
+          x[a] = HnT[jj * HP + gk + a];
+          y[a] = HnT[jj * HP + gl + a];
+        }
+#pragma unroll
+        for (int a = 0; a < TB; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) ga[a][b] = fmaf(x[a], y[b], ga[a][b]);
+      }
+    }
+  }
+  if (gram) {
+    float* out = gout + (int64_t)blockIdx.x * RP * RP;
+#pragma unroll
+    for (int a = 0; a < TB; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) out[(gk + a) * RP + gl + b] = ga[a][b];
   }
 }
 
@@ -798,7 +1011,7 @@ static dim3 tiles3(int64_t M, int64_t N, int bm, int bn, int splits) {
 #define NT_CASE(ID, KERN, T)                                                          \
   case ID:                                                                           \
     hipLaunchKernelGGL((KERN<kNtArgs##ID>), grid, dim3(cfg.threads), 0, st, X, ldx, M, \
-                       Y, ldy, N, K, kchunk, part, ldp, sp);                          \
+                       Y, ldy, N, K, kchunk, part, ldp, sp, gr);                      \
     break;
 
 #define kNtArgs0 2, 1, 4, 1
@@ -815,7 +1028,7 @@ static dim3 tiles3(int64_t M, int64_t N, int bm, int bn, int splits) {
 hipError_t launch_gemm_nt(const NtCfg& cfg, const float* X, int64_t ldx, int64_t M,
                           const float* Y, int64_t ldy, int64_t N, int64_t K, int splits,
                           int64_t kchunk, float* part, int64_t ldp, int64_t sp,
-                          hipStream_t st) {
+                          const GramRed& gr, hipStream_t st) {
   const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
   switch (cfg.id) {
     NT_CASE(0, k_gemm_nt, float)
@@ -836,7 +1049,7 @@ hipError_t launch_gemm_nt(const NtCfg& cfg, const float* X, int64_t ldx, int64_t
 hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X, int64_t ldx, int64_t M,
                                const uint16_t* Y, int64_t ldy, int64_t N, int64_t K,
                                int splits, int64_t kchunk, float* part, int64_t ldp,
-                               int64_t sp, hipStream_t st) {
+                               int64_t sp, const GramRed& gr, hipStream_t st) {
   const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
   switch (cfg.id) {
     NT_CASE(0, k_gemm_nt_bf16, uint16_t)
@@ -857,13 +1070,13 @@ hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X, int64_t ldx,
 #define TN_CASE(ID, MB, WM, WN)                                                         \
   case ID:                                                                             \
     hipLaunchKernelGGL((k_gemm_tn<MB, WM, WN>), grid, dim3(cfg.threads), 0, st, A, lda, \
-                       M, B, ldb, N, K, kchunk, part, ldp, sp);                         \
+                       M, B, ldb, N, K, kchunk, part, ldp, sp, gr);                     \
     break;
 
 hipError_t launch_gemm_tn(const TnCfg& cfg, const float* A, int64_t lda, int64_t M,
                           const float* B, int64_t ldb, int64_t N, int64_t K, int splits,
                           int64_t kchunk, float* part, int64_t ldp, int64_t sp,
-                          hipStream_t st) {
+                          const GramRed& gr, hipStream_t st) {
   const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
   switch (cfg.id) {
     TN_CASE(0, 1, 1, 4)
@@ -880,8 +1093,8 @@ hipError_t launch_gemm_tn(const TnCfg& cfg, const float* A, int64_t lda, int64_t
 
 hipError_t launch_reduce_gram(const float* part, int64_t ldp, int64_t sp, int splits, int rp,
                               float* G, uint16_t* Gbf, hipStream_t st) {
-  const int64_t total = (int64_t)rp * rp;
-  hipLaunchKernelGGL(k_reduce_gram, dim3(grid1d(total, 256)), dim3(256), 0, st, part, ldp, sp,
+  const int64_t total = (int64_t)rp * rp / 4;
+  hipLaunchKernelGGL(k_reduce_gram, dim3(grid1d(total, 64)), dim3(64), 0, st, part, ldp, sp,
                      splits, rp, G, Gbf);
   return hipGetLastError();
 }
@@ -896,26 +1109,38 @@ hipError_t launch_reduce_gram(const float* part, int64_t ldp, int64_t sp, int sp
     default: return hipErrorInvalidValue; \
   }
 
+int update_grid(int rp, int64_t extent, int cap) {
+  const int64_t per = 1024 / (rp < 64 ? rp : 64);  // rows per block of k_update_w
+  int64_t blocks = (extent + per - 1) / per;
+  if (cap > 0 && blocks > cap) blocks = cap;
+  return (int)(blocks < 1 ? 1 : blocks);
+}
+
+int update_h_grid(int64_t n, int cap) {
+  int64_t blocks = (n + 63) / 64;
+  if (cap > 0 && blocks > cap) blocks = cap;
+  return (int)(blocks < 1 ? 1 : blocks);
+}
+
 hipError_t launch_update_w(int rp, int64_t p, int r, const float* part, int64_t ldp, int64_t sp,
                            int splits, const float* G, float* Wp, float* Wcaller,
-                           uint16_t* WbT, int64_t ldwt, bool bf16, hipStream_t st) {
-  const dim3 grid((unsigned)((p + 31) / 32));
-#define UW(R)                                                                                 \
-  hipLaunchKernelGGL(k_update_w<R>, grid, dim3(256), 0, st, p, r, part, ldp, sp, splits, G, Wp, \
-                     Wcaller, WbT, ldwt, (int)bf16)
+                           uint16_t* WbT, int64_t ldwt, bool bf16, float* gout, int grid,
+                           bool gram_only, hipStream_t st) {
+#define UW(R)                                                                                  \
+  hipLaunchKernelGGL(k_update_w<R>, dim3(grid), dim3(256), 0, st, p, r, part, ldp, sp, splits, G, \
+                     Wp, Wcaller, WbT, ldwt, (int)bf16, gout, (int)gram_only)
   RP_SWITCH(rp, UW)
 #undef UW
   return hipGetLastError();
 }
 
 hipError_t launch_update_h(int rp, int64_t n, int r, const float* part, int64_t ldp, int64_t sp,
-                           int splits, bool transposed, const float* G, float* Hp, int64_t ldh,
-                           float* Hcaller, uint16_t* Hb, bool bf16, hipStream_t st) {
-  if (transposed) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((n + 63) / 64));
-#define UH(R)                                                                                 \
-  hipLaunchKernelGGL(k_update_h<R>, grid, dim3(256), 0, st, n, r, part, ldp, sp, splits, G, Hp, \
-                     ldh, Hcaller, Hb, (int)bf16)
+                           int splits, const float* G, float* Hp, int64_t ldh, float* Hcaller,
+                           uint16_t* Hb, bool bf16, float* gout, int grid, bool gram_only,
+                           hipStream_t st) {
+#define UH(R)                                                                                  \
+  hipLaunchKernelGGL(k_update_h<R>, dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, splits, G, \
+                     Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only)
   RP_SWITCH(rp, UH)
 #undef UH
   return hipGetLastError();

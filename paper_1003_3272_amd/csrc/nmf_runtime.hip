@@ -18,8 +18,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/nmf.h"
 #include "nmf_internal.h"
@@ -31,6 +33,14 @@ namespace {
 constexpr int64_t kMaxDim = 4000000;  // objective grid.y = ceil(p / 64) <= 65535
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+int64_t env_int(const char* name, int64_t dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char* end = nullptr;
+  const long long x = std::strtoll(v, &end, 10);
+  return (end && *end == 0 && x > 0) ? (int64_t)x : dflt;
+}
 
 struct Split {
   int splits = 1;
@@ -86,6 +96,8 @@ struct nmf_ctx {
   float* part1 = nullptr;
   float* part2 = nullptr;
   float* partg = nullptr;
+  float* gpw = nullptr;  // per-workgroup Grams of W from the W update (fused path)
+  float* gph = nullptr;  // per-workgroup Grams of H from the H update (fused path)
   double* fpart = nullptr;
   double* fdev = nullptr;
   uint32_t* flag = nullptr;
@@ -97,11 +109,20 @@ struct nmf_ctx {
   double* hostbuf = nullptr;  // pinned, 2 doubles
 
   bool bf16 = false;
+  bool fuse = false;      // rp <= 64: Grams formed in the update kernels
+  int uw_grid = 1, uh_grid = 1;
   NtCfg c1{}, cgh{}, c2b{};
   TnCfg c2{}, cgw{};
   Split s1, s2, sgh, sgw;
   int64_t nparts = 0;
   double nv2 = 0.0;  // ||V||_F^2 in float64
+
+  // stage profiler (HIP events on st)
+  bool prof = false;
+  int32_t prof_cap = 0;
+  std::vector<hipEvent_t> ev;   // 2 per record
+  std::vector<int> ev_stage;    // stage per record
+  int32_t prof_used = 0;
 };
 
 #define TRY_HIP(expr)                      \
@@ -117,6 +138,33 @@ struct nmf_ctx {
 
 namespace {
 
+// Brackets one stage with profiler events when profiling is on.
+struct StageTimer {
+  nmf_ctx* c;
+  int rec = -1;
+  StageTimer(nmf_ctx* ctx, int stage) : c(ctx) {
+    if (c->prof && c->prof_used < c->prof_cap) {
+      rec = c->prof_used++;
+      c->ev_stage[rec] = stage;
+      if (hipEventRecord(c->ev[2 * rec], c->st) != hipSuccess) rec = -1;
+    }
+  }
+  ~StageTimer() {
+    if (rec >= 0) (void)hipEventRecord(c->ev[2 * rec + 1], c->st);
+  }
+};
+
+void profile_release(nmf_ctx* c) {
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_stage.clear();
+  c->prof = false;
+  c->prof_cap = 0;
+  c->prof_used = 0;
+}
+
+const GramRed kNoGram = {nullptr, 0, 0, nullptr};
+
 nmf_status check_ptr(const void* p) {
   if (!p) return NMF_EINVAL;
   if (reinterpret_cast<uintptr_t>(p) % 4 != 0) return NMF_EINVAL;
@@ -125,13 +173,15 @@ nmf_status check_ptr(const void* p) {
 
 // Gram G_H = Hp Hp^T (or its bf16 analogue) from the current H.
 nmf_status gram_h(nmf_ctx* c) {
+  StageTimer t(c, NMF_STAGE_GRAM_H);
   if (c->bf16) {
     TRY_HIP(launch_gemm_nt_bf16(c->cgh, c->Hb, c->npad, c->rp, c->Hb, c->npad, c->rp, c->n,
                                 c->sgh.splits, c->sgh.kchunk, c->partg, c->sgh.ldp, c->sgh.sp,
-                                c->st));
+                                kNoGram, c->st));
   } else {
     TRY_HIP(launch_gemm_nt(c->cgh, c->Hp, c->npad, c->rp, c->Hp, c->npad, c->rp, c->n,
-                           c->sgh.splits, c->sgh.kchunk, c->partg, c->sgh.ldp, c->sgh.sp, c->st));
+                           c->sgh.splits, c->sgh.kchunk, c->partg, c->sgh.ldp, c->sgh.sp, kNoGram,
+                           c->st));
   }
   TRY_HIP(launch_reduce_gram(c->partg, c->sgh.ldp, c->sgh.sp, c->sgh.splits, c->rp, c->GH, nullptr,
                              c->st));
@@ -140,13 +190,14 @@ nmf_status gram_h(nmf_ctx* c) {
 
 // Gram G_W = Wp^T Wp (or its bf16 analogue) from the current W.
 nmf_status gram_w(nmf_ctx* c) {
+  StageTimer t(c, NMF_STAGE_GRAM_W);
   if (c->bf16) {
     TRY_HIP(launch_gemm_nt_bf16(c->cgh, c->WbT, c->ppad, c->rp, c->WbT, c->ppad, c->rp, c->p,
                                 c->sgw.splits, c->sgw.kchunk, c->partg, c->sgw.ldp, c->sgw.sp,
-                                c->st));
+                                kNoGram, c->st));
   } else {
     TRY_HIP(launch_gemm_tn(c->cgw, c->Wp, c->rp, c->rp, c->Wp, c->rp, c->rp, c->p, c->sgw.splits,
-                           c->sgw.kchunk, c->partg, c->sgw.ldp, c->sgw.sp, c->st));
+                           c->sgw.kchunk, c->partg, c->sgw.ldp, c->sgw.sp, kNoGram, c->st));
   }
   TRY_HIP(launch_reduce_gram(c->partg, c->sgw.ldp, c->sgw.sp, c->sgw.splits, c->rp, c->GW, nullptr,
                              c->st));
@@ -154,33 +205,54 @@ nmf_status gram_w(nmf_ctx* c) {
 }
 
 nmf_status half_w(nmf_ctx* c) {
-  if (c->bf16) {
-    TRY_HIP(launch_gemm_nt_bf16(c->c1, c->Vb, c->ldvb, c->p, c->Hb, c->npad, c->rp, c->n,
-                                c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, c->st));
-  } else {
-    TRY_HIP(launch_gemm_nt(c->c1, c->Vk, c->ldvk, c->p, c->Hp, c->npad, c->rp, c->n, c->s1.splits,
-                           c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, c->st));
+  // G_H: reduced inside the product from the H update's per-workgroup Grams
+  const GramRed gr = c->fuse ? GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH} : kNoGram;
+  {
+    StageTimer t(c, NMF_STAGE_GEMM_VHT);
+    if (c->bf16) {
+      TRY_HIP(launch_gemm_nt_bf16(c->c1, c->Vb, c->ldvb, c->p, c->Hb, c->npad, c->rp, c->n,
+                                  c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, gr,
+                                  c->st));
+    } else {
+      TRY_HIP(launch_gemm_nt(c->c1, c->Vk, c->ldvk, c->p, c->Hp, c->npad, c->rp, c->n,
+                             c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, gr,
+                             c->st));
+    }
   }
-  TRY_HIP(launch_update_w(c->rp, c->p, c->r, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits, c->GH,
-                          c->Wp, c->Wuser, c->bf16 ? c->WbT : nullptr, c->ppad, c->bf16, c->st));
-  return gram_w(c);
+  {
+    StageTimer t(c, NMF_STAGE_UPDATE_W);
+    TRY_HIP(launch_update_w(c->rp, c->p, c->r, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits,
+                            c->GH, c->Wp, c->Wuser, c->bf16 ? c->WbT : nullptr, c->ppad, c->bf16,
+                            c->fuse ? c->gpw : nullptr, c->uw_grid, false, c->st));
+  }
+  return c->fuse ? NMF_OK : gram_w(c);
 }
 
 nmf_status half_h(nmf_ctx* c) {
-  if (c->bf16) {
-    TRY_HIP(launch_gemm_nt_bf16(c->c2b, c->WbT, c->ppad, c->rp, c->VTb, c->ldvt, c->n, c->p,
-                                c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, c->st));
-  } else {
-    TRY_HIP(launch_gemm_tn(c->c2, c->Wp, c->rp, c->rp, c->Vk, c->ldvk, c->n, c->p, c->s2.splits,
-                           c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, c->st));
+  const GramRed gr = c->fuse ? GramRed{c->gpw, c->uw_grid, c->rp * c->rp, c->GW} : kNoGram;
+  {
+    StageTimer t(c, NMF_STAGE_GEMM_WTV);
+    if (c->bf16) {
+      TRY_HIP(launch_gemm_nt_bf16(c->c2b, c->WbT, c->ppad, c->rp, c->VTb, c->ldvt, c->n, c->p,
+                                  c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, gr,
+                                  c->st));
+    } else {
+      TRY_HIP(launch_gemm_tn(c->c2, c->Wp, c->rp, c->rp, c->Vk, c->ldvk, c->n, c->p,
+                             c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, gr,
+                             c->st));
+    }
   }
-  TRY_HIP(launch_update_h(c->rp, c->n, c->r, c->part2, c->s2.ldp, c->s2.sp, c->s2.splits, false,
-                          c->GW, c->Hp, c->npad, c->Huser, c->bf16 ? c->Hb : nullptr, c->bf16,
-                          c->st));
-  return gram_h(c);
+  {
+    StageTimer t(c, NMF_STAGE_UPDATE_H);
+    TRY_HIP(launch_update_h(c->rp, c->n, c->r, c->part2, c->s2.ldp, c->s2.sp, c->s2.splits,
+                            c->GW, c->Hp, c->npad, c->Huser, c->bf16 ? c->Hb : nullptr, c->bf16,
+                            c->fuse ? c->gph : nullptr, c->uh_grid, false, c->st));
+  }
+  return c->fuse ? NMF_OK : gram_h(c);
 }
 
 nmf_status objective_async(nmf_ctx* c, const float* Wp) {
+  StageTimer t(c, NMF_STAGE_OBJECTIVE);
   TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart, c->st));
   TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, c->fdev, c->st));
   return NMF_OK;
@@ -195,6 +267,7 @@ nmf_status read_f(nmf_ctx* c, double* f) {
 
 void free_ctx(nmf_ctx* c) {
   if (!c) return;
+  profile_release(c);
   if (c->ws) (void)hipFree(c->ws);
   if (c->hostbuf) (void)hipHostFree(c->hostbuf);
   delete c;
@@ -212,8 +285,10 @@ nmf_status setup(nmf_ctx* c) {
   const bool v_ok = (reinterpret_cast<uintptr_t>(c->Vuser) % 16 == 0) && (c->ldv % 4 == 0);
   c->ldvk = v_ok ? c->ldv : round_up(n, 4);
 
-  // tiles and splits
-  const int64_t target = 1024;
+  // tiles and splits (environment overrides are tuning knobs)
+  const int64_t target = env_int("NMF_SPLIT_TARGET", 512);
+  const int64_t gtarget = env_int("NMF_GRAM_TARGET", 256);
+  const int64_t gmin = env_int("NMF_GRAM_MINSTEPS", 8);
   if (!c->bf16) {
     c->c1 = nt_config(rp, false);
     c->cgh = nt_config(rp, true);
@@ -221,20 +296,24 @@ nmf_status setup(nmf_ctx* c) {
     c->cgw = tn_config(rp, true);
     c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, 32, target, 4);
     c->s2 = plan_split(rp, n, p, c->c2.bm, c->c2.bn, 32, target, 4);
-    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 32, 256, 8);
-    c->sgw = plan_split(rp, rp, p, c->cgw.bm, c->cgw.bn, 32, 256, 8);
+    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 32, gtarget, gmin);
+    c->sgw = plan_split(rp, rp, p, c->cgw.bm, c->cgw.bn, 32, gtarget, gmin);
   } else {
     c->c1 = nt_config(rp, false);
     c->cgh = nt_bf16_config(rp, true);
     c->c2b = nt_bf16_config(rp, false);
     c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, 64, target, 4);
     c->s2 = plan_split(rp, n, p, c->c2b.bm, c->c2b.bn, 64, target, 4);
-    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 64, 256, 8);
-    c->sgw = plan_split(rp, rp, p, c->cgh.bm, c->cgh.bn, 64, 256, 8);
+    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 64, gtarget, gmin);
+    c->sgw = plan_split(rp, rp, p, c->cgh.bm, c->cgh.bn, 64, gtarget, gmin);
     c->ldvb = round_up(n, 8);
     c->ldvt = round_up(p, 8);
   }
   c->nparts = objective_parts(p, n);
+  c->fuse = rp <= 64;
+  const int ucap = c->fuse ? (int)env_int("NMF_UPDATE_CAP", 512) : 0;
+  c->uw_grid = update_grid(rp, p, ucap);
+  c->uh_grid = update_h_grid(n, ucap);
 
   // carve one allocation, 256-byte aligned pieces
   size_t off = 0;
@@ -252,6 +331,8 @@ nmf_status setup(nmf_ctx* c) {
   const size_t o2 = take(sizeof(float) * (size_t)c->s2.splits * c->s2.sp);
   const size_t og = take(sizeof(float) * std::max((size_t)c->sgh.splits * c->sgh.sp,
                                                   (size_t)c->sgw.splits * c->sgw.sp));
+  const size_t ogw = c->fuse ? take(sizeof(float) * (size_t)c->uw_grid * rp * rp) : 0;
+  const size_t ogh = c->fuse ? take(sizeof(float) * (size_t)c->uh_grid * rp * rp) : 0;
   const size_t ofp = take(sizeof(double) * (size_t)c->nparts);
   const size_t ofd = take(sizeof(double) * 2);
   const size_t ofl = take(sizeof(uint32_t) * 4);
@@ -276,6 +357,10 @@ nmf_status setup(nmf_ctx* c) {
   c->part1 = reinterpret_cast<float*>(base + o1);
   c->part2 = reinterpret_cast<float*>(base + o2);
   c->partg = reinterpret_cast<float*>(base + og);
+  if (c->fuse) {
+    c->gpw = reinterpret_cast<float*>(base + ogw);
+    c->gph = reinterpret_cast<float*>(base + ogh);
+  }
   c->fpart = reinterpret_cast<double*>(base + ofp);
   c->fdev = reinterpret_cast<double*>(base + ofd);
   c->flag = reinterpret_cast<uint32_t*>(base + ofl);
@@ -327,8 +412,16 @@ nmf_status setup(nmf_ctx* c) {
   // ||V||_F^2 (objective with W = 0), then the Grams of the start
   TRY(objective_async(c, nullptr));
   TRY(read_f(c, &c->nv2));
-  TRY(gram_h(c));
-  TRY(gram_w(c));
+  if (c->fuse) {
+    // per-workgroup Grams of the start; the first products reduce them
+    TRY_HIP(launch_update_w(rp, p, c->r, nullptr, 0, 0, 0, nullptr, c->Wp, c->Wuser, nullptr, 0,
+                            c->bf16, c->gpw, c->uw_grid, true, c->st));
+    TRY_HIP(launch_update_h(rp, n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, c->npad, c->Huser,
+                            nullptr, c->bf16, c->gph, c->uh_grid, true, c->st));
+  } else {
+    TRY(gram_h(c));
+    TRY(gram_w(c));
+  }
   return NMF_OK;
 }
 
@@ -449,6 +542,48 @@ nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double*
     if (done) return NMF_OK;
   }
   return NMF_ENOTCONVERGED;
+}
+
+nmf_status nmf_profile_start(nmf_ctx* c, int32_t max_records) {
+  if (!c || max_records < 1) return NMF_EINVAL;
+  TRY_HIP(hipStreamSynchronize(c->st));
+  profile_release(c);
+  c->ev.assign(2 * (size_t)max_records, nullptr);
+  c->ev_stage.assign((size_t)max_records, 0);
+  for (size_t i = 0; i < c->ev.size(); ++i) {
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+      c->ev.resize(i);
+      profile_release(c);
+      return NMF_EDEVICE;
+    }
+  }
+  c->prof_cap = max_records;
+  c->prof_used = 0;
+  c->prof = true;
+  return NMF_OK;
+}
+
+nmf_status nmf_profile_stop(nmf_ctx* c, double* ms_host, int32_t* launches_host) {
+  if (!c) return NMF_EINVAL;
+  double ms[NMF_STAGE_COUNT] = {0};
+  int32_t cnt[NMF_STAGE_COUNT] = {0};
+  nmf_status st = NMF_OK;
+  if (hipStreamSynchronize(c->st) != hipSuccess) st = NMF_EDEVICE;
+  for (int32_t i = 0; st == NMF_OK && i < c->prof_used; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) {
+      st = NMF_EDEVICE;
+      break;
+    }
+    ms[c->ev_stage[i]] += t;
+    cnt[c->ev_stage[i]] += 1;
+  }
+  profile_release(c);
+  for (int k = 0; k < NMF_STAGE_COUNT; ++k) {
+    if (ms_host) ms_host[k] = ms[k];
+    if (launches_host) launches_host[k] = cnt[k];
+  }
+  return st;
 }
 
 void nmf_destroy(nmf_ctx* c) {

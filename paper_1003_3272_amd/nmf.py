@@ -25,6 +25,7 @@ NMF_EUNSUPPORTED = -5
 FP32, BF16 = 0, 1
 REL_CHANGE, GAP_NORMALIZED = 0, 1
 MAX_RANK = 256
+STAGES = ("gemm_vht", "update_w", "gram_w", "gemm_wtv", "update_h", "gram_h", "objective")
 
 _PRECISION = {"fp32": FP32, "bf16": BF16}
 _TOL = {"rel_change": REL_CHANGE, "gap": GAP_NORMALIZED, "gap_normalized": GAP_NORMALIZED}
@@ -77,6 +78,10 @@ def load(path: str = LIB_PATH):
     lib.nmf_solve.argtypes = [P, c_int32, POINTER(c_int32), POINTER(c_double),
                               POINTER(c_double), c_int32]
     lib.nmf_solve.restype = c_int32
+    lib.nmf_profile_start.argtypes = [P, c_int32]
+    lib.nmf_profile_start.restype = c_int32
+    lib.nmf_profile_stop.argtypes = [P, POINTER(c_double), POINTER(c_int32)]
+    lib.nmf_profile_stop.restype = c_int32
     lib.nmf_destroy.argtypes = [P]
     lib.nmf_destroy.restype = None
     lib.nmf_strerror.argtypes = [c_int32]
@@ -177,6 +182,16 @@ class Nmf:
             ce = self.opts.check_every
             ntr = min(trace_len, 1 + (it.value + ce - 1) // ce)
         return st == NMF_OK, it.value, f.value, [buf[i] for i in range(ntr)]
+
+    def profile_start(self, max_records: int):
+        self._check(load().nmf_profile_start(self._ctx, int(max_records)), "nmf_profile_start")
+
+    def profile_stop(self):
+        """Returns {stage: (total_ms, launches)} from the HIP-event profiler."""
+        ms = (c_double * len(STAGES))()
+        cnt = (c_int32 * len(STAGES))()
+        self._check(load().nmf_profile_stop(self._ctx, ms, cnt), "nmf_profile_stop")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
     def close(self):
         if self._ctx:
