@@ -279,3 +279,49 @@ def test_full_size_image_like_one_iteration(gpu_lib):
     assert frob_rel(host(Wd), Wo) < 1e-4
     assert frob_rel(host(Hd), Ho) < 1e-4
     ctx.close()
+
+
+# ------------------------------------------------------------------ BF16 tier
+# The BF16 tier rounds every product operand (V, W, H and the r x r Grams) to
+# bfloat16 (RNE) and accumulates in float32 with float32 master factors.  The
+# oracle's bf16=True path rounds the same operands and accumulates in float64,
+# so a half-step differs only by accumulation error, except where a float32
+# Gram entry and its float64 value round to neighbouring bfloat16 numbers
+# (one 2^-8 step in one Gram entry, diluted over r terms of a denominator).
+@pytest.mark.parametrize("p,n,r", [(300, 700, 24), (513, 1030, 64), (200, 900, 100),
+                                   (160, 300, 230)])
+def test_bf16_half_steps_vs_emulated_oracle(gpu_lib, p, n, r):
+    V, _, _ = g.sparse_planted(p, n, max(1, r // 2), seed=40 + r)
+    V = V + np.float32(1e-3)
+    W0, H0 = g.uniform_init(p, n, r, seed=41 + r)
+    ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0, precision="bf16")
+    for _ in range(2):
+        Win, Hin = host(Wd), host(Hd)
+        ctx.update_w()
+        Wref = o.update_w(V, Win, Hin, bf16=True)
+        err = np.abs(host(Wd) - Wref) / Wref
+        assert err.max() < 2e-3 and np.median(err) < 1e-5, (err.max(), np.median(err))
+        Win = host(Wd)
+        ctx.update_h()
+        Href = o.update_h(V, Win, Hin, bf16=True)
+        err = np.abs(host(Hd) - Href) / Href
+        assert err.max() < 2e-3 and np.median(err) < 1e-5, (err.max(), np.median(err))
+    ctx.close()
+
+
+def test_bf16_objective_close_to_fp64_after_many_iterations(gpu_lib):
+    """1024 x 4096 planted rank 32, 300 iterations: the BF16 tier's objective
+    is within 1e-2 relative of the FP64 oracle's (and descends)."""
+    V, _, _ = g.sparse_planted(1024, 4096, 32, seed=1035)
+    W0, H0 = g.uniform_init(1024, 4096, 32, seed=2035)
+    ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0, precision="bf16")
+    fs = [ctx.objective()]
+    for _ in range(6):
+        ctx.step(50)
+        fs.append(ctx.objective())
+    _, _, tr = o.run(V, W0, H0, 300)
+    rel = abs(fs[-1] - tr[-1]) / tr[-1]
+    print(f"bf16 vs fp64 oracle after 300 iterations: rel diff {rel:.3e}")
+    assert rel < 1e-2
+    assert np.all(np.diff(fs) < 0)
+    ctx.close()
