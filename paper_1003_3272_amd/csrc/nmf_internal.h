@@ -24,6 +24,8 @@ struct NtCfg {
   int id;      // template instance
   int bm, bn;  // tile
   int threads;
+  int bk;       // reduction slots per LDS stage (float32)
+  int bk_bf16;  // reduction slots per LDS stage (bf16)
 };
 // Tile shape of the "TN" product  C[m][c] = sum_k A[k][m] * B[k][c]
 // (both operands contiguous along the output dimension, k the row index).
@@ -31,6 +33,7 @@ struct TnCfg {
   int id;
   int bm, bn;
   int threads;
+  int bk;
 };
 
 // Gram reduction carried by a product kernel (see gram_reduce_slice):
@@ -44,6 +47,10 @@ struct GramRed {
 };
 
 NtCfg nt_config(int rp, bool gram);
+NtCfg nt_config_by_id(int id);
+TnCfg tn_config_by_id(int id);
+int nt_config_count();
+int tn_config_count();
 TnCfg tn_config(int rp, bool gram);
 NtCfg nt_bf16_config(int rp, bool gram);
 

@@ -101,18 +101,18 @@ __device__ __forceinline__ void gram_reduce_slice(const GramRed& g) {
 
 // ---------------------------------------------------------------------------
 // NT product, FP32:  part[s][m][c] = sum_{k in split s} X[m][k] * Y[c][k].
-// Workgroup tile BM x BN, BK = 32 reduction slots per LDS stage, WM x WN
+// Workgroup tile BM x BN, BK reduction slots per LDS stage, WM x WN
 // waves each owning (16 MB) x (16 NB) outputs.  Each lane reads 4
 // consecutive k of a row with one 128-bit LDS load and feeds them to four
 // MFMAs (slot g of MFMA t is k = 4g + t), so A and B see the same k order.
 // Grid: x = N tiles, y = M tiles, z = splits.
 // ---------------------------------------------------------------------------
-template <int MB, int NB, int WM, int WN>
+template <int MB, int NB, int WM, int WN, int BK>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(
     const float* __restrict__ X, int64_t ldx, int64_t M,
     const float* __restrict__ Y, int64_t ldy, int64_t N, int64_t K,
     int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
-  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, BK = 32, PITCH = BK + 4;
+  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, PITCH = BK + 4;
   constexpr int T = 64 * WM * WN;
   constexpr int XQ = BM * (BK / 4), YQ = BN * (BK / 4);
   constexpr int XL = (XQ + T - 1) / T, YL = (YQ + T - 1) / T;
@@ -203,15 +203,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(
 
 // ---------------------------------------------------------------------------
 // NT product, BF16 operands (RNE copies), FP32 accumulation, 16x16x32 MFMA.
-// BK = 64 bf16 per stage; a lane reads 8 consecutive k (one 128-bit LDS
-// load) per operand per MFMA.
+// BK bf16 per stage (a multiple of 32); a lane reads 8 consecutive k (one
+// 128-bit LDS load) per operand per MFMA.
 // ---------------------------------------------------------------------------
-template <int MB, int NB, int WM, int WN>
+template <int MB, int NB, int WM, int WN, int BK>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt_bf16(
     const uint16_t* __restrict__ X, int64_t ldx, int64_t M,
     const uint16_t* __restrict__ Y, int64_t ldy, int64_t N, int64_t K,
     int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
-  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, BK = 64, PITCH = BK + 8;
+  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, PITCH = BK + 8;
   constexpr int T = 64 * WM * WN;
   constexpr int XQ = BM * (BK / 8), YQ = BN * (BK / 8);
   constexpr int XL = (XQ + T - 1) / T, YL = (YQ + T - 1) / T;
@@ -336,13 +336,13 @@ __device__ __forceinline__ float vget<4>(const v4f& v, int i) {
   return v[i];
 }
 
-template <int MB, int WM, int WN>
+template <int MB, int WM, int WN, int BK>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(
     const float* __restrict__ A, int64_t lda, int64_t M,
     const float* __restrict__ B, int64_t ldb, int64_t N, int64_t K,
     int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
   constexpr int NB = 4;
-  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, BK = 32;
+  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN;
   constexpr int PA = BM + 4, PB = BN + 4;
   constexpr int T = 64 * WM * WN;
   constexpr int AQ = BK * (BM / 4), BQ = BK * (BN / 4);
@@ -924,23 +924,107 @@ inline unsigned grid1d(int64_t total, int threads, int64_t cap = 65536) {
 // ---------------------------------------------------------------------------
 // Configurations and launchers
 // ---------------------------------------------------------------------------
-// NT instances: id -> (MB, NB, WM, WN)
-//  0: 2,1,4,1 (128 x 16)   1: 2,2,4,1 (128 x 32)   2: 2,4,4,1 (128 x 64)
-//  3: 4,4,2,2 (128 x 128)  4: 1,1,1,1 (16 x 16)    5: 2,2,1,1 (32 x 32)
-//  6: 2,2,2,2 (64 x 64)    7: 1,4,1,4 (16 x 256)   8: 2,4,1,4 (32 x 256)
-//  9: 4,4,1,4 (64 x 256)
-static const int kNt[10][4] = {{2, 1, 4, 1}, {2, 2, 4, 1}, {2, 4, 4, 1}, {4, 4, 2, 2},
-                               {1, 1, 1, 1}, {2, 2, 1, 1}, {2, 2, 2, 2}, {1, 4, 1, 4},
-                               {2, 4, 1, 4}, {4, 4, 1, 4}};
+typedef hipError_t (*NtLaunch)(const void*, int64_t, int64_t, const void*, int64_t, int64_t,
+                               int64_t, int64_t, float*, int64_t, int64_t, const GramRed&, dim3,
+                               hipStream_t);
+
+template <int MB, int NB, int WM, int WN, int BK>
+hipError_t nt_f32(const void* X, int64_t ldx, int64_t M, const void* Y, int64_t ldy, int64_t N,
+                  int64_t K, int64_t kchunk, float* part, int64_t ldp, int64_t sp,
+                  const GramRed& gr, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemm_nt<MB, NB, WM, WN, BK>), grid, dim3(64 * WM * WN), 0, st,
+                     static_cast<const float*>(X), ldx, M, static_cast<const float*>(Y), ldy, N,
+                     K, kchunk, part, ldp, sp, gr);
+  return hipGetLastError();
+}
+
+template <int MB, int NB, int WM, int WN, int BK>
+hipError_t nt_bf16(const void* X, int64_t ldx, int64_t M, const void* Y, int64_t ldy, int64_t N,
+                   int64_t K, int64_t kchunk, float* part, int64_t ldp, int64_t sp,
+                   const GramRed& gr, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemm_nt_bf16<MB, NB, WM, WN, BK>), grid, dim3(64 * WM * WN), 0, st,
+                     static_cast<const uint16_t*>(X), ldx, M, static_cast<const uint16_t*>(Y),
+                     ldy, N, K, kchunk, part, ldp, sp, gr);
+  return hipGetLastError();
+}
+
+template <int MB, int WM, int WN, int BK>
+hipError_t tn_f32(const void* A, int64_t lda, int64_t M, const void* B, int64_t ldb, int64_t N,
+                  int64_t K, int64_t kchunk, float* part, int64_t ldp, int64_t sp,
+                  const GramRed& gr, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemm_tn<MB, WM, WN, BK>), grid, dim3(64 * WM * WN), 0, st,
+                     static_cast<const float*>(A), lda, M, static_cast<const float*>(B), ldb, N,
+                     K, kchunk, part, ldp, sp, gr);
+  return hipGetLastError();
+}
+
+struct NtEntry {
+  int mb, nb, wm, wn, bk;
+  NtLaunch f32, bf16;
+};
+#define NTE(MB, NB, WM, WN, BK, BKH) \
+  {MB, NB, WM, WN, BK, &nt_f32<MB, NB, WM, WN, BK>, &nt_bf16<MB, NB, WM, WN, BKH>}
+// id: (MB, NB, WM, WN, BK fp32 / BK bf16); tile (16 MB WM) x (16 NB WN)
+static const NtEntry kNt[] = {
+    NTE(2, 1, 4, 1, 32, 64),  //  0: 128 x 16
+    NTE(2, 2, 4, 1, 32, 64),  //  1: 128 x 32
+    NTE(2, 4, 4, 1, 32, 64),  //  2: 128 x 64
+    NTE(4, 4, 2, 2, 32, 64),  //  3: 128 x 128
+    NTE(1, 1, 1, 1, 32, 64),  //  4: 16 x 16
+    NTE(2, 2, 1, 1, 32, 64),  //  5: 32 x 32
+    NTE(2, 2, 2, 2, 32, 64),  //  6: 64 x 64
+    NTE(1, 4, 1, 4, 32, 64),  //  7: 16 x 256
+    NTE(2, 4, 1, 4, 32, 64),  //  8: 32 x 256
+    NTE(4, 4, 1, 4, 32, 64),  //  9: 64 x 256
+    NTE(2, 2, 4, 2, 32, 64),  // 10: 128 x 64, 8 waves
+};
+#undef NTE
+static const int kNtCount = sizeof(kNt) / sizeof(kNt[0]);
+
+struct TnEntry {
+  int mb, wm, wn, bk;
+  NtLaunch f32;
+};
+#define TNE(MB, WM, WN, BK) {MB, WM, WN, BK, &tn_f32<MB, WM, WN, BK>}
+// id: (MB, WM, WN, BK); tile (16 MB WM) x (64 WN)
+static const TnEntry kTn[] = {
+    TNE(1, 1, 4, 32),  //  0: 16 x 256
+    TNE(2, 1, 4, 32),  //  1: 32 x 256
+    TNE(4, 1, 4, 32),  //  2: 64 x 256
+    TNE(4, 2, 2, 32),  //  3: 128 x 128
+    TNE(1, 1, 1, 32),  //  4: 16 x 64
+    TNE(2, 1, 1, 32),  //  5: 32 x 64
+    TNE(4, 1, 1, 32),  //  6: 64 x 64
+    TNE(2, 2, 4, 32),  //  7: 64 x 256, 8 waves
+};
+#undef TNE
+static const int kTnCount = sizeof(kTn) / sizeof(kTn[0]);
 
 static NtCfg make_nt(int id) {
   NtCfg c;
   c.id = id;
-  c.bm = 16 * kNt[id][0] * kNt[id][2];
-  c.bn = 16 * kNt[id][1] * kNt[id][3];
-  c.threads = 64 * kNt[id][2] * kNt[id][3];
+  c.bm = 16 * kNt[id].mb * kNt[id].wm;
+  c.bn = 16 * kNt[id].nb * kNt[id].wn;
+  c.threads = 64 * kNt[id].wm * kNt[id].wn;
+  c.bk = kNt[id].bk;
+  c.bk_bf16 = 2 * kNt[id].bk;
   return c;
 }
+
+static TnCfg make_tn(int id) {
+  TnCfg c;
+  c.id = id;
+  c.bm = 16 * kTn[id].mb * kTn[id].wm;
+  c.bn = 64 * kTn[id].wn;
+  c.threads = 64 * kTn[id].wm * kTn[id].wn;
+  c.bk = kTn[id].bk;
+  return c;
+}
+
+int nt_config_count() { return kNtCount; }
+int tn_config_count() { return kTnCount; }
+NtCfg nt_config_by_id(int id) { return make_nt(id < 0 || id >= kNtCount ? 2 : id); }
+TnCfg tn_config_by_id(int id) { return make_tn(id < 0 || id >= kTnCount ? 2 : id); }
 
 NtCfg nt_config(int rp, bool gram) {
   if (gram) {
@@ -971,22 +1055,6 @@ NtCfg nt_bf16_config(int rp, bool gram) {
   }
 }
 
-// TN instances: id -> (MB, WM, WN); tile (16 MB WM) x (64 WN)
-//  0: 1,1,4 (16 x 256)  1: 2,1,4 (32 x 256)  2: 4,1,4 (64 x 256)
-//  3: 4,2,2 (128 x 128) 4: 1,1,1 (16 x 64)   5: 2,1,1 (32 x 64)
-//  6: 4,1,1 (64 x 64)
-static const int kTn[7][3] = {{1, 1, 4}, {2, 1, 4}, {4, 1, 4}, {4, 2, 2},
-                              {1, 1, 1}, {2, 1, 1}, {4, 1, 1}};
-
-static TnCfg make_tn(int id) {
-  TnCfg c;
-  c.id = id;
-  c.bm = 16 * kTn[id][0] * kTn[id][1];
-  c.bn = 64 * kTn[id][2];
-  c.threads = 64 * kTn[id][1] * kTn[id][2];
-  return c;
-}
-
 TnCfg tn_config(int rp, bool gram) {
   if (gram) {
     switch (rp) {
@@ -1008,87 +1076,31 @@ static dim3 tiles3(int64_t M, int64_t N, int bm, int bn, int splits) {
   return dim3((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), (unsigned)splits);
 }
 
-#define NT_CASE(ID, KERN, T)                                                          \
-  case ID:                                                                           \
-    hipLaunchKernelGGL((KERN<kNtArgs##ID>), grid, dim3(cfg.threads), 0, st, X, ldx, M, \
-                       Y, ldy, N, K, kchunk, part, ldp, sp, gr);                      \
-    break;
-
-#define kNtArgs0 2, 1, 4, 1
-#define kNtArgs1 2, 2, 4, 1
-#define kNtArgs2 2, 4, 4, 1
-#define kNtArgs3 4, 4, 2, 2
-#define kNtArgs4 1, 1, 1, 1
-#define kNtArgs5 2, 2, 1, 1
-#define kNtArgs6 2, 2, 2, 2
-#define kNtArgs7 1, 4, 1, 4
-#define kNtArgs8 2, 4, 1, 4
-#define kNtArgs9 4, 4, 1, 4
-
 hipError_t launch_gemm_nt(const NtCfg& cfg, const float* X, int64_t ldx, int64_t M,
                           const float* Y, int64_t ldy, int64_t N, int64_t K, int splits,
                           int64_t kchunk, float* part, int64_t ldp, int64_t sp,
                           const GramRed& gr, hipStream_t st) {
-  const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
-  switch (cfg.id) {
-    NT_CASE(0, k_gemm_nt, float)
-    NT_CASE(1, k_gemm_nt, float)
-    NT_CASE(2, k_gemm_nt, float)
-    NT_CASE(3, k_gemm_nt, float)
-    NT_CASE(4, k_gemm_nt, float)
-    NT_CASE(5, k_gemm_nt, float)
-    NT_CASE(6, k_gemm_nt, float)
-    NT_CASE(7, k_gemm_nt, float)
-    NT_CASE(8, k_gemm_nt, float)
-    NT_CASE(9, k_gemm_nt, float)
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (cfg.id < 0 || cfg.id >= kNtCount) return hipErrorInvalidValue;
+  return kNt[cfg.id].f32(X, ldx, M, Y, ldy, N, K, kchunk, part, ldp, sp, gr,
+                         tiles3(M, N, cfg.bm, cfg.bn, splits), st);
 }
 
 hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X, int64_t ldx, int64_t M,
                                const uint16_t* Y, int64_t ldy, int64_t N, int64_t K,
                                int splits, int64_t kchunk, float* part, int64_t ldp,
                                int64_t sp, const GramRed& gr, hipStream_t st) {
-  const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
-  switch (cfg.id) {
-    NT_CASE(0, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(1, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(2, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(3, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(4, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(5, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(6, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(7, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(8, k_gemm_nt_bf16, uint16_t)
-    NT_CASE(9, k_gemm_nt_bf16, uint16_t)
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (cfg.id < 0 || cfg.id >= kNtCount) return hipErrorInvalidValue;
+  return kNt[cfg.id].bf16(X, ldx, M, Y, ldy, N, K, kchunk, part, ldp, sp, gr,
+                          tiles3(M, N, cfg.bm, cfg.bn, splits), st);
 }
-
-#define TN_CASE(ID, MB, WM, WN)                                                         \
-  case ID:                                                                             \
-    hipLaunchKernelGGL((k_gemm_tn<MB, WM, WN>), grid, dim3(cfg.threads), 0, st, A, lda, \
-                       M, B, ldb, N, K, kchunk, part, ldp, sp, gr);                     \
-    break;
 
 hipError_t launch_gemm_tn(const TnCfg& cfg, const float* A, int64_t lda, int64_t M,
                           const float* B, int64_t ldb, int64_t N, int64_t K, int splits,
                           int64_t kchunk, float* part, int64_t ldp, int64_t sp,
                           const GramRed& gr, hipStream_t st) {
-  const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
-  switch (cfg.id) {
-    TN_CASE(0, 1, 1, 4)
-    TN_CASE(1, 2, 1, 4)
-    TN_CASE(2, 4, 1, 4)
-    TN_CASE(3, 4, 2, 2)
-    TN_CASE(4, 1, 1, 1)
-    TN_CASE(5, 2, 1, 1)
-    TN_CASE(6, 4, 1, 1)
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (cfg.id < 0 || cfg.id >= kTnCount) return hipErrorInvalidValue;
+  return kTn[cfg.id].f32(A, lda, M, B, ldb, N, K, kchunk, part, ldp, sp, gr,
+                         tiles3(M, N, cfg.bm, cfg.bn, splits), st);
 }
 
 hipError_t launch_reduce_gram(const float* part, int64_t ldp, int64_t sp, int splits, int rp,

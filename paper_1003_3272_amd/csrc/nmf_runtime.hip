@@ -294,18 +294,22 @@ nmf_status setup(nmf_ctx* c) {
     c->cgh = nt_config(rp, true);
     c->c2 = tn_config(rp, false);
     c->cgw = tn_config(rp, true);
-    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, 32, target, 4);
-    c->s2 = plan_split(rp, n, p, c->c2.bm, c->c2.bn, 32, target, 4);
-    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 32, gtarget, gmin);
-    c->sgw = plan_split(rp, rp, p, c->cgw.bm, c->cgw.bn, 32, gtarget, gmin);
+    if (env_int("NMF_CFG1", -1) >= 0) c->c1 = nt_config_by_id((int)env_int("NMF_CFG1", 0));
+    if (env_int("NMF_CFG2", -1) >= 0) c->c2 = tn_config_by_id((int)env_int("NMF_CFG2", 0));
+    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, c->c1.bk, target, 4);
+    c->s2 = plan_split(rp, n, p, c->c2.bm, c->c2.bn, c->c2.bk, env_int("NMF_SPLIT_TARGET2", target), 4);
+    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, c->cgh.bk, gtarget, gmin);
+    c->sgw = plan_split(rp, rp, p, c->cgw.bm, c->cgw.bn, c->cgw.bk, gtarget, gmin);
   } else {
     c->c1 = nt_config(rp, false);
     c->cgh = nt_bf16_config(rp, true);
     c->c2b = nt_bf16_config(rp, false);
-    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, 64, target, 4);
-    c->s2 = plan_split(rp, n, p, c->c2b.bm, c->c2b.bn, 64, target, 4);
-    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, 64, gtarget, gmin);
-    c->sgw = plan_split(rp, rp, p, c->cgh.bm, c->cgh.bn, 64, gtarget, gmin);
+    if (env_int("NMF_CFG1", -1) >= 0) c->c1 = nt_config_by_id((int)env_int("NMF_CFG1", 0));
+    if (env_int("NMF_CFG2B", -1) >= 0) c->c2b = nt_config_by_id((int)env_int("NMF_CFG2B", 0));
+    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, c->c1.bk_bf16, target, 4);
+    c->s2 = plan_split(rp, n, p, c->c2b.bm, c->c2b.bn, c->c2b.bk_bf16, env_int("NMF_SPLIT_TARGET2", target), 4);
+    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, c->cgh.bk_bf16, gtarget, gmin);
+    c->sgw = plan_split(rp, rp, p, c->cgh.bm, c->cgh.bn, c->cgh.bk_bf16, gtarget, gmin);
     c->ldvb = round_up(n, 8);
     c->ldvt = round_up(p, 8);
   }
