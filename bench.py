@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--p", type=int, default=4096)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--r", type=int, default=64)
+    ap.add_argument("--ldv-pad", type=int, default=0,
+                    help="extra floats per V row in device memory (row-stride experiment)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the FP64 oracle baseline sample (0 disables)")
     return ap.parse_args()
@@ -82,7 +84,11 @@ def main():
     V, _, _ = gen.sparse_planted(p, n, r, seed=1002)
     W0, H0 = gen.uniform_init(p, n, r, seed=2002)
     dev = torch.device("cuda:0")
-    Vd = torch.from_numpy(V).to(dev)
+    if args.ldv_pad > 0:
+        Vd = torch.zeros((p, n + args.ldv_pad), dtype=torch.float32, device=dev)[:, :n]
+        Vd.copy_(torch.from_numpy(V).to(dev))
+    else:
+        Vd = torch.from_numpy(V).to(dev)
     Wd = torch.from_numpy(W0).to(dev)
     Hd = torch.from_numpy(H0).to(dev)
     stream = torch.cuda.current_stream()

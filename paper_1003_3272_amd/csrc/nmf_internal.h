@@ -68,6 +68,23 @@ hipError_t launch_gemm_tn(const TnCfg& cfg, const float* A, int64_t lda,
                           int64_t ldp, int64_t sp, const GramRed& gr,
                           hipStream_t st);
 
+// ---- V-streaming NT product through an asynchronous LDS ring ------------
+// part[s][m][c] = sum_k X[m][k] Y[c][k], float32 or bf16 operands (float32
+// accumulation).  X and Y rows must be readable up to round_up(M, bm) and
+// round_up(N, bn) and along k up to K, with zeros beyond the data; K and
+// kchunk multiples of 256; pitches (in elements) multiples of 64 bytes.
+struct DmaCfg {
+  int id;
+  int bm, bn;
+  int threads;
+};
+DmaCfg dma_config(int rp, bool pass1);
+DmaCfg dma_config_by_id(int id);
+hipError_t launch_nt_dma(const DmaCfg& cfg, bool bf16, const void* X, int64_t ldx,
+                         int64_t M, const void* Y, int64_t ldy, int64_t N, int64_t K,
+                         int splits, int64_t kchunk, float* part, int64_t ldp,
+                         int64_t sp, const GramRed& gr, hipStream_t st);
+
 // ---- BF16 NT product (16x16x32 MFMA, FP32 accumulation) ------------------
 hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X,
                                int64_t ldx, int64_t M, const uint16_t* Y,
@@ -87,12 +104,13 @@ int update_h_grid(int64_t n, int cap);
 
 // W half-step epilogue.  Wp (ppad x rp) holds the current W; A partials are
 // part[s][i][k] (pitch ldp, split pitch sp).  Writes the new W to Wp, to the
-// caller's W (p x r) and, for the BF16 tier, to WbT (rp x ldwt, transposed).
+// caller's W (p x r) and, when given, to WT (float32) or WbT (bf16), both
+// transposed (rp x ldwt).
 // gout != nullptr (rp <= 64): also writes per-workgroup Grams of the new W
 // (grid x rp x rp).  gram_only: no update, Grams of the current W only.
 hipError_t launch_update_w(int rp, int64_t p, int r, const float* part,
                            int64_t ldp, int64_t sp, int splits, const float* G,
-                           float* Wp, float* Wcaller, uint16_t* WbT,
+                           float* Wp, float* Wcaller, float* WT, uint16_t* WbT,
                            int64_t ldwt, bool bf16, float* gout, int grid,
                            bool gram_only, hipStream_t st);
 
@@ -126,6 +144,10 @@ hipError_t launch_fill_u32(uint32_t* dst, int64_t count, uint32_t v,
 hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t rows,
                             int64_t cols, uint16_t* dst, int64_t ldd,
                             bool transpose, hipStream_t st);
+// dst[j][i] = src[i][j] (float32), pitch ldd.
+hipError_t launch_transpose_f32(const float* src, int64_t lds, int64_t rows,
+                                int64_t cols, float* dst, int64_t ldd,
+                                hipStream_t st);
 // flag |= 1 if some V entry is negative or non-finite.
 hipError_t launch_validate(const float* V, int64_t ldv, int64_t p, int64_t n,
                            uint32_t* flag, hipStream_t st);

@@ -427,6 +427,164 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(
 }
 
 // ---------------------------------------------------------------------------
+// V-streaming product through an asynchronous LDS ring:
+//   part[s][m][c] = sum_{k in split s} X[m][k] * Y[c][k]
+// with X and Y contiguous along k and padded with zeros so that every tile
+// is in bounds (rows to a multiple of the tile, k to a multiple of 256).
+// A stage is BM + BN rows of 128 bytes (32 floats or 64 bf16 of k).  It is
+// copied global -> LDS by global_load_lds_dwordx4 (the data never passes
+// through registers) and S stages are in flight at once, so the load
+// latency is covered by S - 1 stages of MFMA work.  Inside a row, 16-byte
+// chunk q is stored at slot q ^ (row % 8): the 16 lanes of an MFMA fragment
+// (rows c = 0..15, same chunk) then hit distinct LDS banks.
+// FP32: a chunk is 4 k-values, fed to 4 v_mfma_f32_16x16x4_f32 (slot g of
+// MFMA t is k = 16 kk + 4 g + t).  BF16: a chunk is the 8 k-values a lane
+// supplies to one v_mfma_f32_16x16x32_bf16.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// s_waitcnt vmcnt(VM) (gfx9 encoding, vmcnt split over bits 3:0 and
+// 15:14), leaving expcnt and lgkmcnt unconstrained.
+template <int VM>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(VM >= 0 && VM < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((VM & 0xF) | (0x7 << 4) | (0xF << 8) | (((VM >> 4) & 0x3) << 14));
+}
+
+// Workgroup barrier for the copy ring.  __syncthreads() (and any LDS
+// release fence) would drain every outstanding global->LDS copy, because
+// their completion is counted by vmcnt; the ring instead waits for exactly
+// its own stage (wait_stage) and then meets at a bare s_barrier.  The empty
+// asm statements keep the compiler from moving LDS accesses across it, and
+// lgkmcnt(0) retires this wave's own LDS reads first.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int L, int S>
+__device__ __forceinline__ void wait_stage(int after) {
+  // my loads of the stage being consumed are done once at most
+  // L * after loads (those of the `after` later stages) are outstanding
+  if (S >= 4 && after >= 3) wait_vm<(S >= 4 ? 3 * L : 0)>();
+  else if (after >= 2) wait_vm<2 * L>();
+  else if (after == 1) wait_vm<L>();
+  else wait_vm<0>();
+}
+
+template <int MB, int NB, int WM, int WN, int S, bool BF>
+__global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
+    const void* __restrict__ Xv, int64_t ldx, const void* __restrict__ Yv, int64_t ldy,
+    int64_t K, int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
+  constexpr int ES = BF ? 2 : 4;
+  constexpr int BKE = 128 / ES;
+  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, ROWS = BM + BN;
+  constexpr int W = WM * WN;
+  static_assert(ROWS % (8 * W) == 0, "stage rows must split evenly over the waves");
+  constexpr int L = ROWS / (8 * W);  // DMA instructions per wave per stage
+  constexpr int STAGE = ROWS * 128;  // bytes
+  __shared__ __attribute__((aligned(1024))) char lds[S * STAGE];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int c = lane & 15, g = lane >> 4;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (K < kb + kchunk) ? K : kb + kchunk;
+  const int nst = (int)((ke - kb) / BKE);
+  gram_reduce_slice(gr);
+
+  // source of this lane in each of the wave's L copy instructions: row
+  // rr = 8 (wave L + j) + lane / 8 of the stage, slot lane % 8, which holds
+  // chunk (lane % 8) ^ (rr % 8) = (lane % 8) ^ (lane / 8)
+  const char* X = static_cast<const char*>(Xv);
+  const char* Y = static_cast<const char*>(Yv);
+  const int chunk = (lane & 7) ^ (lane >> 3);
+  const char* src[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const int rr = 8 * (wave * L + j) + (lane >> 3);
+    src[j] = rr < BM ? X + ((m0 + rr) * ldx + kb) * ES + 16 * chunk
+                     : Y + ((n0 + rr - BM) * ldy + kb) * ES + 16 * chunk;
+  }
+  auto issue = [&](int st) {
+    char* dst = lds + (st % S) * STAGE;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(src[j] + (int64_t)st * 128),
+                                       (lds_ptr_t)(dst + (wave * L + j) * 1024), 16, 0, 0);
+  };
+
+  v4f acc[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](const char* buf) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int q = 4 * kk + g;
+      const int off = 16 * (q ^ (c & 7));
+      if constexpr (BF) {
+        v8bf a[MB], b[NB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+          a[i] = *reinterpret_cast<const v8bf*>(buf + (wm * 16 * MB + 16 * i + c) * 128 + off);
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          b[j] = *reinterpret_cast<const v8bf*>(buf + (BM + wn * 16 * NB + 16 * j + c) * 128 + off);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+      } else {
+        v4f a[MB], b[NB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+          a[i] = *reinterpret_cast<const v4f*>(buf + (wm * 16 * MB + 16 * i + c) * 128 + off);
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          b[j] = *reinterpret_cast<const v4f*>(buf + (BM + wn * 16 * NB + 16 * j + c) * 128 + off);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[i][j] = mfma_f32(a[i][t], b[j][t], acc[i][j]);
+      }
+    }
+  };
+
+  const int pre = nst < S - 1 ? nst : S - 1;
+  for (int st = 0; st < pre; ++st) issue(st);
+  for (int st = 0; st < nst; ++st) {
+    if (st + S - 1 < nst) {
+      lds_barrier();  // every wave is done with the buffer about to be refilled
+      issue(st + S - 1);
+    }
+    const int later = nst - 1 - st;
+    wait_stage<L, S>(later < S - 1 ? later : S - 1);
+    lds_barrier();  // every wave's copies of this stage have landed
+    compute(lds + (st % S) * STAGE);
+  }
+
+  float* P = part + (int64_t)blockIdx.z * sp;
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * 16 * MB + 16 * i + 4 * g + v;
+        const int64_t col = n0 + wn * 16 * NB + 16 * j + c;
+        P[row * ldp + col] = acc[i][j][v];
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Split-K sums.  The partial tiles are summed in ascending split order; the
 // loads of 8 splits are issued together before the (ordered) adds so the
 // loop is not a chain of dependent memory round trips.
@@ -488,7 +646,7 @@ template <int RP>
 __global__ __launch_bounds__(256) void k_update_w(
     int64_t p, int r, const float* __restrict__ part, int64_t ldp, int64_t sp,
     int splits, const float* __restrict__ G, float* __restrict__ Wp,
-    float* __restrict__ Wc, uint16_t* __restrict__ WbT, int64_t ldwt,
+    float* __restrict__ Wc, float* __restrict__ WT, uint16_t* __restrict__ WbT, int64_t ldwt,
     int bf16, float* __restrict__ gout, int gram_only) {
   constexpr int KC = RP < 64 ? RP : 64;
   constexpr int ROWS = 1024 / KC;
@@ -559,6 +717,7 @@ __global__ __launch_bounds__(256) void k_update_w(
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             if (k + e < r) Wc[row * r + k + e] = wv[e];
+            if (WT) WT[(int64_t)(k + e) * ldwt + row] = wv[e];
             if (WbT) WbT[(int64_t)(k + e) * ldwt + row] = to_bf16(wv[e]);
           }
         }
@@ -843,19 +1002,32 @@ __global__ void k_fill_u32(uint32_t* __restrict__ dst, int64_t count, uint32_t v
     dst[idx] = v;
 }
 
-// Cast to bf16 through a 32 x 32 LDS tile; with `transpose` the tile is
-// written out transposed so both reads and writes stay coalesced.
-__global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src,
-                                                   int64_t lds, int64_t rows,
-                                                   int64_t cols, uint16_t* __restrict__ dst,
-                                                   int64_t ldd, int transpose) {
-  __shared__ uint16_t t[32][33];
+// Copy (float32, or bfloat16 RNE) through a 32 x 32 LDS tile; with
+// `transpose` the tile is written out transposed so both reads and writes
+// stay coalesced.
+template <typename OutT>
+__device__ __forceinline__ OutT convert_out(float x);
+template <>
+__device__ __forceinline__ float convert_out<float>(float x) {
+  return x;
+}
+template <>
+__device__ __forceinline__ uint16_t convert_out<uint16_t>(float x) {
+  return to_bf16(x);
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_convert(const float* __restrict__ src, int64_t lds,
+                                                 int64_t rows, int64_t cols,
+                                                 OutT* __restrict__ dst, int64_t ldd,
+                                                 int transpose) {
+  __shared__ OutT t[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
   for (int q = 0; q < 4; ++q) {
     const int64_t i = r0 + ty + 8 * q, j = c0 + tx;
-    uint16_t h = 0;
-    if (i < rows && j < cols) h = to_bf16(src[i * lds + j]);
+    OutT h = OutT(0);
+    if (i < rows && j < cols) h = convert_out<OutT>(src[i * lds + j]);
     if (!transpose) {
       if (i < rows && j < cols) dst[i * ldd + j] = h;
     } else {
@@ -1094,6 +1266,65 @@ hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X, int64_t ldx,
                           tiles3(M, N, cfg.bm, cfg.bn, splits), st);
 }
 
+typedef hipError_t (*DmaLaunch)(const void*, int64_t, const void*, int64_t, int64_t, int64_t,
+                                float*, int64_t, int64_t, const GramRed&, dim3, hipStream_t);
+
+template <int MB, int NB, int WM, int WN, int S, bool BF>
+hipError_t dma_inst(const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t K,
+                    int64_t kchunk, float* part, int64_t ldp, int64_t sp, const GramRed& gr,
+                    dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_nt_dma<MB, NB, WM, WN, S, BF>), grid, dim3(64 * WM * WN), 0, st, X, ldx,
+                     Y, ldy, K, kchunk, part, ldp, sp, gr);
+  return hipGetLastError();
+}
+
+struct DmaEntry {
+  int mb, nb, wm, wn, s;
+  DmaLaunch f32, bf16;
+};
+#define DME(MB, NB, WM, WN, S) \
+  {MB, NB, WM, WN, S, &dma_inst<MB, NB, WM, WN, S, false>, &dma_inst<MB, NB, WM, WN, S, true>}
+// id: (MB, NB, WM, WN, stages); tile (16 MB WM) x (16 NB WN)
+static const DmaEntry kDma[] = {
+    DME(4, 1, 2, 1, 3),  // 0: 128 x 16   pass 1, r <= 16
+    DME(2, 2, 4, 1, 3),  // 1: 128 x 32   pass 1, r <= 32
+    DME(2, 4, 4, 1, 3),  // 2: 128 x 64   pass 1, r <= 64
+    DME(4, 4, 2, 2, 2),  // 3: 128 x 128  r > 64
+    DME(1, 4, 1, 2, 3),  // 4: 16 x 128   pass 2, r <= 16
+    DME(1, 4, 2, 2, 3),  // 5: 32 x 128   pass 2, r <= 32
+    DME(2, 4, 2, 2, 3),  // 6: 64 x 128   pass 2, r <= 64
+    DME(2, 4, 4, 1, 4),  // 7: 128 x 64, 4 stages
+    DME(2, 4, 2, 2, 4),  // 8: 64 x 128, 4 stages
+};
+#undef DME
+static const int kDmaCount = sizeof(kDma) / sizeof(kDma[0]);
+
+DmaCfg dma_config_by_id(int id) {
+  if (id < 0 || id >= kDmaCount) id = 2;
+  DmaCfg c;
+  c.id = id;
+  c.bm = 16 * kDma[id].mb * kDma[id].wm;
+  c.bn = 16 * kDma[id].nb * kDma[id].wn;
+  c.threads = 64 * kDma[id].wm * kDma[id].wn;
+  return c;
+}
+
+DmaCfg dma_config(int rp, bool pass1) {
+  if (rp > 64) return dma_config_by_id(3);
+  if (pass1) return dma_config_by_id(rp == 16 ? 0 : rp == 32 ? 1 : 2);
+  return dma_config_by_id(rp == 16 ? 4 : rp == 32 ? 5 : 6);
+}
+
+hipError_t launch_nt_dma(const DmaCfg& cfg, bool bf16, const void* X, int64_t ldx, int64_t M,
+                         const void* Y, int64_t ldy, int64_t N, int64_t K, int splits,
+                         int64_t kchunk, float* part, int64_t ldp, int64_t sp, const GramRed& gr,
+                         hipStream_t st) {
+  if (cfg.id < 0 || cfg.id >= kDmaCount) return hipErrorInvalidValue;
+  const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
+  return bf16 ? kDma[cfg.id].bf16(X, ldx, Y, ldy, K, kchunk, part, ldp, sp, gr, grid, st)
+              : kDma[cfg.id].f32(X, ldx, Y, ldy, K, kchunk, part, ldp, sp, gr, grid, st);
+}
+
 hipError_t launch_gemm_tn(const TnCfg& cfg, const float* A, int64_t lda, int64_t M,
                           const float* B, int64_t ldb, int64_t N, int64_t K, int splits,
                           int64_t kchunk, float* part, int64_t ldp, int64_t sp,
@@ -1135,12 +1366,12 @@ int update_h_grid(int64_t n, int cap) {
 }
 
 hipError_t launch_update_w(int rp, int64_t p, int r, const float* part, int64_t ldp, int64_t sp,
-                           int splits, const float* G, float* Wp, float* Wcaller,
+                           int splits, const float* G, float* Wp, float* Wcaller, float* WT,
                            uint16_t* WbT, int64_t ldwt, bool bf16, float* gout, int grid,
                            bool gram_only, hipStream_t st) {
 #define UW(R)                                                                                  \
   hipLaunchKernelGGL(k_update_w<R>, dim3(grid), dim3(256), 0, st, p, r, part, ldp, sp, splits, G, \
-                     Wp, Wcaller, WbT, ldwt, (int)bf16, gout, (int)gram_only)
+                     Wp, Wcaller, WT, WbT, ldwt, (int)bf16, gout, (int)gram_only)
   RP_SWITCH(rp, UW)
 #undef UW
   return hipGetLastError();
@@ -1196,8 +1427,15 @@ hipError_t launch_fill_u32(uint32_t* dst, int64_t count, uint32_t v, hipStream_t
 hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t rows, int64_t cols,
                             uint16_t* dst, int64_t ldd, bool transpose, hipStream_t st) {
   const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
-  hipLaunchKernelGGL(k_cast_bf16, grid, dim3(256), 0, st, src, lds, rows, cols, dst, ldd,
+  hipLaunchKernelGGL(k_convert<uint16_t>, grid, dim3(256), 0, st, src, lds, rows, cols, dst, ldd,
                      (int)transpose);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_f32(const float* src, int64_t lds, int64_t rows, int64_t cols,
+                                float* dst, int64_t ldd, hipStream_t st) {
+  const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  hipLaunchKernelGGL(k_convert<float>, grid, dim3(256), 0, st, src, lds, rows, cols, dst, ldd, 1);
   return hipGetLastError();
 }
 

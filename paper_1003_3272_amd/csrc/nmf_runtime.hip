@@ -7,12 +7,16 @@
 //   H half-step:  S = W^T V (split-K partials)  ->  H <- H * S / (G_W H)
 //                 -> G_H = H H^T                     (for the next W half-step)
 //
-// Internal layout (row-major, zero padded):
-//   Wp   ppad x rp        ppad = round_up(p, 256), rp = padded rank
-//   Hp   rp x npad        npad = round_up(n, 256)
-//   G_H, G_W  rp x rp
-//   BF16 tier: Vb (p x ldvb) and VTb (n x ldvt) = bf16(V) and bf16(V^T),
-//              Hb (rp x npad), WbT (rp x ppad) = bf16(H) and bf16(W^T).
+// Internal layout (row-major, zero padded; ppad = round_up(p, 256),
+// npad = round_up(n, 256), rp = padded rank):
+//   Wp (ppad x rp), Hp (rp x npad), G_H and G_W (rp x rp)
+//   FP32:  V itself when p, n are multiples of 256 (else a ppad x npad copy),
+//          VT = V^T (npad x ppad), WT = W^T (rp x ppad)
+//   BF16:  Vb = bf16(V) (ppad x npad), VTb = bf16(V^T) (npad x ppad),
+//          Hb = bf16(H) (rp x npad), WbT = bf16(W^T) (rp x ppad)
+// Both V-streaming products are NT products through the LDS copy ring:
+//   pass 1  A = V H^T   X = V / Vb,   Y = Hp / Hb,  K = npad
+//   pass 2  S = W^T V   X = WT / WbT, Y = VT / VTb, K = ppad
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,7 +43,7 @@ int64_t env_int(const char* name, int64_t dflt) {
   if (!v || !*v) return dflt;
   char* end = nullptr;
   const long long x = std::strtoll(v, &end, 10);
-  return (end && *end == 0 && x > 0) ? (int64_t)x : dflt;
+  return (end && *end == 0 && x >= 0) ? (int64_t)x : dflt;
 }
 
 struct Split {
@@ -101,18 +105,20 @@ struct nmf_ctx {
   double* fpart = nullptr;
   double* fdev = nullptr;
   uint32_t* flag = nullptr;
+  float* VT = nullptr;
+  float* WT = nullptr;
   uint16_t* Vb = nullptr;
   uint16_t* VTb = nullptr;
   uint16_t* Hb = nullptr;
   uint16_t* WbT = nullptr;
-  int64_t ldvb = 0, ldvt = 0;
   double* hostbuf = nullptr;  // pinned, 2 doubles
 
   bool bf16 = false;
   bool fuse = false;      // rp <= 64: Grams formed in the update kernels
   int uw_grid = 1, uh_grid = 1;
-  NtCfg c1{}, cgh{}, c2b{};
-  TnCfg c2{}, cgw{};
+  DmaCfg d1{}, d2{};      // the two V-streaming products
+  NtCfg cgh{};            // separate Gram products (rp > 64)
+  TnCfg cgw{};
   Split s1, s2, sgh, sgw;
   int64_t nparts = 0;
   double nv2 = 0.0;  // ||V||_F^2 in float64
@@ -209,20 +215,17 @@ nmf_status half_w(nmf_ctx* c) {
   const GramRed gr = c->fuse ? GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH} : kNoGram;
   {
     StageTimer t(c, NMF_STAGE_GEMM_VHT);
-    if (c->bf16) {
-      TRY_HIP(launch_gemm_nt_bf16(c->c1, c->Vb, c->ldvb, c->p, c->Hb, c->npad, c->rp, c->n,
-                                  c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, gr,
-                                  c->st));
-    } else {
-      TRY_HIP(launch_gemm_nt(c->c1, c->Vk, c->ldvk, c->p, c->Hp, c->npad, c->rp, c->n,
-                             c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, gr,
-                             c->st));
-    }
+    const void* X = c->bf16 ? static_cast<const void*>(c->Vb) : static_cast<const void*>(c->Vk);
+    const void* Y = c->bf16 ? static_cast<const void*>(c->Hb) : static_cast<const void*>(c->Hp);
+    TRY_HIP(launch_nt_dma(c->d1, c->bf16, X, c->bf16 ? c->npad : c->ldvk, c->p, Y, c->npad,
+                          c->rp, c->npad, c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp,
+                          c->s1.sp, gr, c->st));
   }
   {
     StageTimer t(c, NMF_STAGE_UPDATE_W);
     TRY_HIP(launch_update_w(c->rp, c->p, c->r, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits,
-                            c->GH, c->Wp, c->Wuser, c->bf16 ? c->WbT : nullptr, c->ppad, c->bf16,
+                            c->GH, c->Wp, c->Wuser, c->bf16 ? nullptr : c->WT,
+                            c->bf16 ? c->WbT : nullptr, c->ppad, c->bf16,
                             c->fuse ? c->gpw : nullptr, c->uw_grid, false, c->st));
   }
   return c->fuse ? NMF_OK : gram_w(c);
@@ -232,15 +235,10 @@ nmf_status half_h(nmf_ctx* c) {
   const GramRed gr = c->fuse ? GramRed{c->gpw, c->uw_grid, c->rp * c->rp, c->GW} : kNoGram;
   {
     StageTimer t(c, NMF_STAGE_GEMM_WTV);
-    if (c->bf16) {
-      TRY_HIP(launch_gemm_nt_bf16(c->c2b, c->WbT, c->ppad, c->rp, c->VTb, c->ldvt, c->n, c->p,
-                                  c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, gr,
-                                  c->st));
-    } else {
-      TRY_HIP(launch_gemm_tn(c->c2, c->Wp, c->rp, c->rp, c->Vk, c->ldvk, c->n, c->p,
-                             c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, gr,
-                             c->st));
-    }
+    const void* X = c->bf16 ? static_cast<const void*>(c->WbT) : static_cast<const void*>(c->WT);
+    const void* Y = c->bf16 ? static_cast<const void*>(c->VTb) : static_cast<const void*>(c->VT);
+    TRY_HIP(launch_nt_dma(c->d2, c->bf16, X, c->ppad, c->rp, Y, c->ppad, c->n, c->ppad,
+                          c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, gr, c->st));
   }
   {
     StageTimer t(c, NMF_STAGE_UPDATE_H);
@@ -278,43 +276,43 @@ nmf_status setup(nmf_ctx* c) {
   const int rp = c->rp;
   c->ppad = round_up(p, 256);
   c->npad = round_up(n, 256);
+  const int64_t ppad = c->ppad, npad = c->npad;
   c->bf16 = (c->opt.precision == NMF_BF16);
 
-  // V as seen by the FP32 kernels: the caller's buffer when it is 16-byte
-  // aligned with a row stride that keeps rows aligned, else a padded copy.
-  const bool v_ok = (reinterpret_cast<uintptr_t>(c->Vuser) % 16 == 0) && (c->ldv % 4 == 0);
-  c->ldvk = v_ok ? c->ldv : round_up(n, 4);
+  // V as read by the float32 kernels.  The copy ring reads whole tiles, so
+  // the FP32 tier uses the caller's buffer only when its rows are 16-byte
+  // aligned and p, n are multiples of 256; otherwise (and for misaligned
+  // rows in the BF16 tier, whose products read the bf16 shadows) a
+  // zero-padded ppad x npad copy.
+  const bool aligned = (reinterpret_cast<uintptr_t>(c->Vuser) % 16 == 0) && (c->ldv % 4 == 0);
+  const bool need_copy = !aligned || (!c->bf16 && (p % 256 != 0 || n % 256 != 0));
+  c->ldvk = need_copy ? npad : c->ldv;
 
   // tiles and splits (environment overrides are tuning knobs)
   const int64_t target = env_int("NMF_SPLIT_TARGET", 512);
+  const int64_t target2 = env_int("NMF_SPLIT_TARGET2", target);
   const int64_t gtarget = env_int("NMF_GRAM_TARGET", 256);
   const int64_t gmin = env_int("NMF_GRAM_MINSTEPS", 8);
-  if (!c->bf16) {
-    c->c1 = nt_config(rp, false);
-    c->cgh = nt_config(rp, true);
-    c->c2 = tn_config(rp, false);
-    c->cgw = tn_config(rp, true);
-    if (env_int("NMF_CFG1", -1) >= 0) c->c1 = nt_config_by_id((int)env_int("NMF_CFG1", 0));
-    if (env_int("NMF_CFG2", -1) >= 0) c->c2 = tn_config_by_id((int)env_int("NMF_CFG2", 0));
-    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, c->c1.bk, target, 4);
-    c->s2 = plan_split(rp, n, p, c->c2.bm, c->c2.bn, c->c2.bk, env_int("NMF_SPLIT_TARGET2", target), 4);
-    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, c->cgh.bk, gtarget, gmin);
-    c->sgw = plan_split(rp, rp, p, c->cgw.bm, c->cgw.bn, c->cgw.bk, gtarget, gmin);
-  } else {
-    c->c1 = nt_config(rp, false);
-    c->cgh = nt_bf16_config(rp, true);
-    c->c2b = nt_bf16_config(rp, false);
-    if (env_int("NMF_CFG1", -1) >= 0) c->c1 = nt_config_by_id((int)env_int("NMF_CFG1", 0));
-    if (env_int("NMF_CFG2B", -1) >= 0) c->c2b = nt_config_by_id((int)env_int("NMF_CFG2B", 0));
-    c->s1 = plan_split(p, rp, n, c->c1.bm, c->c1.bn, c->c1.bk_bf16, target, 4);
-    c->s2 = plan_split(rp, n, p, c->c2b.bm, c->c2b.bn, c->c2b.bk_bf16, env_int("NMF_SPLIT_TARGET2", target), 4);
-    c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, c->cgh.bk_bf16, gtarget, gmin);
-    c->sgw = plan_split(rp, rp, p, c->cgh.bm, c->cgh.bn, c->cgh.bk_bf16, gtarget, gmin);
-    c->ldvb = round_up(n, 8);
-    c->ldvt = round_up(p, 8);
+  c->d1 = dma_config(rp, true);
+  c->d2 = dma_config(rp, false);
+  if (env_int("NMF_DMA1", -1) >= 0) c->d1 = dma_config_by_id((int)env_int("NMF_DMA1", 0));
+  if (env_int("NMF_DMA2", -1) >= 0) c->d2 = dma_config_by_id((int)env_int("NMF_DMA2", 0));
+  c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
+  c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
+  c->fuse = rp <= 64;
+  if (!c->fuse) {
+    if (!c->bf16) {
+      c->cgh = nt_config(rp, true);
+      c->cgw = tn_config(rp, true);
+      c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, c->cgh.bk, gtarget, gmin);
+      c->sgw = plan_split(rp, rp, p, c->cgw.bm, c->cgw.bn, c->cgw.bk, gtarget, gmin);
+    } else {
+      c->cgh = nt_bf16_config(rp, true);
+      c->sgh = plan_split(rp, rp, n, c->cgh.bm, c->cgh.bn, c->cgh.bk_bf16, gtarget, gmin);
+      c->sgw = plan_split(rp, rp, p, c->cgh.bm, c->cgh.bn, c->cgh.bk_bf16, gtarget, gmin);
+    }
   }
   c->nparts = objective_parts(p, n);
-  c->fuse = rp <= 64;
   const int ucap = c->fuse ? (int)env_int("NMF_UPDATE_CAP", 512) : 0;
   c->uw_grid = update_grid(rp, p, ucap);
   c->uh_grid = update_h_grid(n, ucap);
@@ -326,26 +324,30 @@ nmf_status setup(nmf_ctx* c) {
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  const size_t oVc = v_ok ? 0 : take(sizeof(float) * (size_t)p * c->ldvk);
-  const size_t oWp = take(sizeof(float) * (size_t)c->ppad * rp);
-  const size_t oHp = take(sizeof(float) * (size_t)rp * c->npad);
+  const size_t oVc = need_copy ? take(sizeof(float) * (size_t)ppad * npad) : 0;
+  const size_t oWp = take(sizeof(float) * (size_t)ppad * rp);
+  const size_t oHp = take(sizeof(float) * (size_t)rp * npad);
   const size_t oGH = take(sizeof(float) * (size_t)rp * rp);
   const size_t oGW = take(sizeof(float) * (size_t)rp * rp);
   const size_t o1 = take(sizeof(float) * (size_t)c->s1.splits * c->s1.sp);
   const size_t o2 = take(sizeof(float) * (size_t)c->s2.splits * c->s2.sp);
-  const size_t og = take(sizeof(float) * std::max((size_t)c->sgh.splits * c->sgh.sp,
-                                                  (size_t)c->sgw.splits * c->sgw.sp));
+  const size_t og = c->fuse ? 0
+                            : take(sizeof(float) * std::max((size_t)c->sgh.splits * c->sgh.sp,
+                                                            (size_t)c->sgw.splits * c->sgw.sp));
   const size_t ogw = c->fuse ? take(sizeof(float) * (size_t)c->uw_grid * rp * rp) : 0;
   const size_t ogh = c->fuse ? take(sizeof(float) * (size_t)c->uh_grid * rp * rp) : 0;
   const size_t ofp = take(sizeof(double) * (size_t)c->nparts);
   const size_t ofd = take(sizeof(double) * 2);
   const size_t ofl = take(sizeof(uint32_t) * 4);
-  size_t oVb = 0, oVTb = 0, oHb = 0, oWbT = 0;
-  if (c->bf16) {
-    oVb = take(sizeof(uint16_t) * (size_t)p * c->ldvb);
-    oVTb = take(sizeof(uint16_t) * (size_t)n * c->ldvt);
-    oHb = take(sizeof(uint16_t) * (size_t)rp * c->npad);
-    oWbT = take(sizeof(uint16_t) * (size_t)rp * c->ppad);
+  size_t oVT = 0, oWT = 0, oVb = 0, oVTb = 0, oHb = 0, oWbT = 0;
+  if (!c->bf16) {
+    oVT = take(sizeof(float) * (size_t)npad * ppad);
+    oWT = take(sizeof(float) * (size_t)rp * ppad);
+  } else {
+    oVb = take(sizeof(uint16_t) * (size_t)ppad * npad);
+    oVTb = take(sizeof(uint16_t) * (size_t)npad * ppad);
+    oHb = take(sizeof(uint16_t) * (size_t)rp * npad);
+    oWbT = take(sizeof(uint16_t) * (size_t)rp * ppad);
   }
   if (hipMalloc(&c->ws, off) != hipSuccess) {
     c->ws = nullptr;
@@ -353,14 +355,14 @@ nmf_status setup(nmf_ctx* c) {
     return NMF_ENOMEM;
   }
   char* base = static_cast<char*>(c->ws);
-  if (!v_ok) c->Vcopy = reinterpret_cast<float*>(base + oVc);
+  if (need_copy) c->Vcopy = reinterpret_cast<float*>(base + oVc);
   c->Wp = reinterpret_cast<float*>(base + oWp);
   c->Hp = reinterpret_cast<float*>(base + oHp);
   c->GH = reinterpret_cast<float*>(base + oGH);
   c->GW = reinterpret_cast<float*>(base + oGW);
   c->part1 = reinterpret_cast<float*>(base + o1);
   c->part2 = reinterpret_cast<float*>(base + o2);
-  c->partg = reinterpret_cast<float*>(base + og);
+  if (!c->fuse) c->partg = reinterpret_cast<float*>(base + og);
   if (c->fuse) {
     c->gpw = reinterpret_cast<float*>(base + ogw);
     c->gph = reinterpret_cast<float*>(base + ogh);
@@ -368,7 +370,10 @@ nmf_status setup(nmf_ctx* c) {
   c->fpart = reinterpret_cast<double*>(base + ofp);
   c->fdev = reinterpret_cast<double*>(base + ofd);
   c->flag = reinterpret_cast<uint32_t*>(base + ofl);
-  if (c->bf16) {
+  if (!c->bf16) {
+    c->VT = reinterpret_cast<float*>(base + oVT);
+    c->WT = reinterpret_cast<float*>(base + oWT);
+  } else {
     c->Vb = reinterpret_cast<uint16_t*>(base + oVb);
     c->VTb = reinterpret_cast<uint16_t*>(base + oVTb);
     c->Hb = reinterpret_cast<uint16_t*>(base + oHb);
@@ -392,7 +397,7 @@ nmf_status setup(nmf_ctx* c) {
     if (bad) return NMF_EINVAL;
   }
 
-  if (!v_ok) {
+  if (need_copy) {
     TRY_HIP(launch_copy_pad(c->Vuser, c->ldv, p, n, c->Vcopy, c->ldvk, c->st));
     c->Vk = c->Vcopy;
   } else {
@@ -404,13 +409,16 @@ nmf_status setup(nmf_ctx* c) {
     TRY_HIP(launch_uniform(c->Huser, c->r, n, n, c->opt.seed, 1u, c->st));
   }
   TRY_HIP(launch_copy_pad(c->Wuser, c->r, p, c->r, c->Wp, rp, c->st));
-  TRY_HIP(launch_copy_pad(c->Huser, n, c->r, n, c->Hp, c->npad, c->st));
+  TRY_HIP(launch_copy_pad(c->Huser, n, c->r, n, c->Hp, npad, c->st));
 
-  if (c->bf16) {
-    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->Vb, c->ldvb, false, c->st));
-    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->VTb, c->ldvt, true, c->st));
-    TRY_HIP(launch_cast_bf16(c->Hp, c->npad, rp, c->npad, c->Hb, c->npad, false, c->st));
-    TRY_HIP(launch_cast_bf16(c->Wp, rp, c->ppad, rp, c->WbT, c->ppad, true, c->st));
+  if (!c->bf16) {
+    TRY_HIP(launch_transpose_f32(c->Vk, c->ldvk, p, n, c->VT, ppad, c->st));
+    TRY_HIP(launch_transpose_f32(c->Wp, rp, ppad, rp, c->WT, ppad, c->st));
+  } else {
+    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->Vb, npad, false, c->st));
+    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->VTb, ppad, true, c->st));
+    TRY_HIP(launch_cast_bf16(c->Hp, npad, rp, npad, c->Hb, npad, false, c->st));
+    TRY_HIP(launch_cast_bf16(c->Wp, rp, ppad, rp, c->WbT, ppad, true, c->st));
   }
 
   // ||V||_F^2 (objective with W = 0), then the Grams of the start
@@ -418,9 +426,9 @@ nmf_status setup(nmf_ctx* c) {
   TRY(read_f(c, &c->nv2));
   if (c->fuse) {
     // per-workgroup Grams of the start; the first products reduce them
-    TRY_HIP(launch_update_w(rp, p, c->r, nullptr, 0, 0, 0, nullptr, c->Wp, c->Wuser, nullptr, 0,
-                            c->bf16, c->gpw, c->uw_grid, true, c->st));
-    TRY_HIP(launch_update_h(rp, n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, c->npad, c->Huser,
+    TRY_HIP(launch_update_w(rp, p, c->r, nullptr, 0, 0, 0, nullptr, c->Wp, c->Wuser, nullptr,
+                            nullptr, 0, c->bf16, c->gpw, c->uw_grid, true, c->st));
+    TRY_HIP(launch_update_h(rp, n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, npad, c->Huser,
                             nullptr, c->bf16, c->gph, c->uh_grid, true, c->st));
   } else {
     TRY(gram_h(c));
