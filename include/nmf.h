@@ -78,10 +78,14 @@ typedef struct {
                            generator keyed by seed (Algorithm 1's
                            initialization); zero: start from the caller's
                            W and H                                          */
+  int32_t use_graph;    /* nonzero: nmf_step replays the iteration's kernels
+                           from a captured HIP graph (fewer launch gaps);
+                           results are identical to direct launches        */
+  int32_t reserved;     /* must be 0                                        */
 } nmf_options;
 
 /* Fill *opt with defaults: FP32, REL_CHANGE, tol 1e-9, check_every 1,
-   validate 0, seed 0.  NULL is ignored. */
+   validate 0, seed 0, use_graph 1.  NULL is ignored. */
 void nmf_default_options(nmf_options* opt);
 
 /* Create a context for V (p x n, row stride ldv) and rank r, reading the
@@ -99,7 +103,10 @@ nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n,
 
 /* Enqueue `iters` (>= 0) full iterations of Algorithm 1 (NNMF): the W
    update of eq. nnmf_v_update followed by the H update of eq.
-   nnmf_w_update with the new W.  Asynchronous; no host synchronization. */
+   nnmf_w_update with the new W.  Asynchronous; no host synchronization.
+   With use_graph the iterations are replayed from HIP graphs captured on
+   first use (while the profiler is running, kernels are launched directly
+   so that every stage can be timed). */
 nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
 
 /* Enqueue only the W half-step (eq. nnmf_v_update):

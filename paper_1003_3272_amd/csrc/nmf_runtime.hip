@@ -35,6 +35,7 @@ using namespace nmfk;
 namespace {
 
 constexpr int64_t kMaxDim = 4000000;  // objective grid.y = ceil(p / 64) <= 65535
+constexpr int32_t kGraphChunk = 16;    // iterations per replay of the large graph
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -122,6 +123,10 @@ struct nmf_ctx {
   Split s1, s2, sgh, sgw;
   int64_t nparts = 0;
   double nv2 = 0.0;  // ||V||_F^2 in float64
+
+  // captured iterations (use_graph): graphs of 1 and kGraphChunk iterations
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t g1 = nullptr, gk = nullptr;
 
   // stage profiler (HIP events on st)
   bool prof = false;
@@ -266,9 +271,41 @@ nmf_status read_f(nmf_ctx* c, double* f) {
 void free_ctx(nmf_ctx* c) {
   if (!c) return;
   profile_release(c);
+  if (c->g1) (void)hipGraphExecDestroy(c->g1);
+  if (c->gk) (void)hipGraphExecDestroy(c->gk);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->ws) (void)hipFree(c->ws);
   if (c->hostbuf) (void)hipHostFree(c->hostbuf);
   delete c;
+}
+
+// Capture `iters` iterations launched on a private stream into an
+// executable graph.  The kernels' arguments are fixed for the context's
+// life, so a graph can be replayed on any stream.
+nmf_status capture(nmf_ctx* c, int32_t iters, hipGraphExec_t* out) {
+  if (!c->cap_stream) TRY_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = c->st;
+  c->st = c->cap_stream;
+  hipGraph_t graph = nullptr;
+  nmf_status s = NMF_OK;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->st = user;
+    return NMF_EDEVICE;
+  }
+  for (int32_t it = 0; it < iters && s == NMF_OK; ++it) {
+    s = half_w(c);
+    if (s == NMF_OK) s = half_h(c);
+  }
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  c->st = user;
+  if (s != NMF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess || !graph) return NMF_EDEVICE;
+  const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  return ei == hipSuccess ? NMF_OK : NMF_EDEVICE;
 }
 
 nmf_status setup(nmf_ctx* c) {
@@ -449,6 +486,8 @@ void nmf_default_options(nmf_options* opt) {
   opt->check_every = 1;
   opt->validate = 0;
   opt->seed = 0;
+  opt->use_graph = 1;
+  opt->reserved = 0;
 }
 
 nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n, int64_t ldv, int32_t r,
@@ -462,7 +501,8 @@ nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n, int64_t
   TRY(check_ptr(V));
   TRY(check_ptr(W));
   TRY(check_ptr(H));
-  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol)) return NMF_EINVAL;
+  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol) || o.reserved != 0)
+    return NMF_EINVAL;
   if (o.precision != NMF_FP32 && o.precision != NMF_BF16) return NMF_EUNSUPPORTED;
   if (o.tol_kind != NMF_TOL_REL_CHANGE && o.tol_kind != NMF_TOL_GAP_NORMALIZED)
     return NMF_EUNSUPPORTED;
@@ -507,9 +547,21 @@ nmf_status nmf_update_h(nmf_ctx* c) {
 
 nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
   if (!c || iters < 0) return NMF_EINVAL;
-  for (int32_t it = 0; it < iters; ++it) {
-    TRY(half_w(c));
-    TRY(half_h(c));
+  if (!c->opt.use_graph || c->prof) {
+    for (int32_t it = 0; it < iters; ++it) {
+      TRY(half_w(c));
+      TRY(half_h(c));
+    }
+    return NMF_OK;
+  }
+  int32_t left = iters;
+  if (left >= kGraphChunk) {
+    if (!c->gk) TRY(capture(c, kGraphChunk, &c->gk));
+    for (; left >= kGraphChunk; left -= kGraphChunk) TRY_HIP(hipGraphLaunch(c->gk, c->st));
+  }
+  if (left > 0) {
+    if (!c->g1) TRY(capture(c, 1, &c->g1));
+    for (; left > 0; --left) TRY_HIP(hipGraphLaunch(c->g1, c->st));
   }
   return NMF_OK;
 }

@@ -39,6 +39,8 @@ class NmfOptions(ctypes.Structure):
         ("check_every", c_int32),
         ("validate", c_int32),
         ("seed", c_uint64),
+        ("use_graph", c_int32),
+        ("reserved", c_int32),
     ]
 
 
@@ -97,7 +99,7 @@ def strerror(status: int) -> str:
 
 
 def options(precision="fp32", tol_kind="rel_change", tol=1e-9, check_every=1,
-            validate=False, seed=0) -> NmfOptions:
+            validate=False, seed=0, use_graph=True) -> NmfOptions:
     o = NmfOptions()
     load().nmf_default_options(byref(o))
     o.precision = _PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -106,6 +108,7 @@ def options(precision="fp32", tol_kind="rel_change", tol=1e-9, check_every=1,
     o.check_every = int(check_every)
     o.validate = 1 if validate else 0
     o.seed = int(seed)
+    o.use_graph = 1 if use_graph else 0
     return o
 
 
@@ -123,7 +126,7 @@ class Nmf:
     """
 
     def __init__(self, V, W, H, precision="fp32", tol_kind="rel_change", tol=1e-9,
-                 check_every=1, validate=False, seed=0, stream=None):
+                 check_every=1, validate=False, seed=0, use_graph=True, stream=None):
         import torch
         lib = load()
         for name, t in (("V", V), ("W", W), ("H", H)):
@@ -140,7 +143,7 @@ class Nmf:
         self._keep = (V, W, H)
         self.V, self.W, self.H = V, W, H
         self.p, self.n, self.r = p, n, r
-        self.opts = options(precision, tol_kind, tol, check_every, validate, seed)
+        self.opts = options(precision, tol_kind, tol, check_every, validate, seed, use_graph)
         self.stream = stream
         self._ctx = c_void_p()
         st = lib.nmf_init(byref(self._ctx), c_void_p(V.data_ptr()), p, n, V.stride(0), r,

@@ -122,3 +122,14 @@ def image_like(p=4096, n=16384, r=64, seed=1002, init_seed=2002):
 def precision_tier(r, p=8192, n=32768):
     """8192 x 32768 planted rank r, seed 1003 + r, init seed 2003 + r."""
     return image_like(p, n, r, seed=1003 + r, init_seed=2003 + r)
+
+
+def mlp_init(p, d, r, seed):
+    """Warm-start network parameters [M1 (d x p), b1, M2 (r x d), b2]:
+    He-uniform M1, Glorot-uniform M2, zero biases, float32."""
+    rng = np.random.default_rng(seed)
+    a1 = np.sqrt(6.0 / p)
+    a2 = np.sqrt(6.0 / (d + r))
+    M1 = rng.uniform(-a1, a1, size=(d, p)).astype(np.float32)
+    M2 = rng.uniform(-a2, a2, size=(r, d)).astype(np.float32)
+    return [M1, np.zeros(d, np.float32), M2, np.zeros(r, np.float32)]

@@ -36,17 +36,18 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_options_struct_layout_matches_header():
-    # int32, int32, double, int32, int32, uint64 -> 32 bytes, double at 8
-    assert ctypes.sizeof(nmf.NmfOptions) == 32
+    # int32, int32, double, int32, int32, uint64, int32, int32 -> 40 bytes
+    assert ctypes.sizeof(nmf.NmfOptions) == 40
     assert nmf.NmfOptions.tol.offset == 8
     assert nmf.NmfOptions.seed.offset == 24
+    assert nmf.NmfOptions.use_graph.offset == 32
 
 
 def test_default_options():
     o = nmf.NmfOptions()
     nmf.load().nmf_default_options(ctypes.byref(o))
-    assert (o.precision, o.tol_kind, o.tol, o.check_every, o.validate, o.seed) == \
-        (0, 0, 1e-9, 1, 0, 0)
+    assert (o.precision, o.tol_kind, o.tol, o.check_every, o.validate, o.seed,
+            o.use_graph, o.reserved) == (0, 0, 1e-9, 1, 0, 0, 1, 0)
 
 
 def test_strerror_and_version():
@@ -96,6 +97,7 @@ def test_init_rejects_rank_above_max():
     ("tol", float("inf"), nmf.NMF_EINVAL),
     ("precision", 7, nmf.NMF_EUNSUPPORTED),
     ("tol_kind", 5, nmf.NMF_EUNSUPPORTED),
+    ("reserved", 3, nmf.NMF_EINVAL),
 ])
 def test_init_rejects_bad_options(field, value, code):
     o = nmf.options()

@@ -325,3 +325,26 @@ def test_bf16_objective_close_to_fp64_after_many_iterations(gpu_lib):
     assert rel < 1e-2
     assert np.all(np.diff(fs) < 0)
     ctx.close()
+
+
+def test_graph_replay_matches_direct_launches(gpu_lib):
+    """nmf_step replays captured graphs (16-iteration and 1-iteration); every
+    replay, interleaved with eager work (objective, half-steps), must give the
+    same bits as direct launches."""
+    V, W0, H0 = g.image_like(600, 1100, 24, seed=61, init_seed=62)
+    a, _, Wa, Ha = make(gpu_lib, V, W0, H0, use_graph=True)
+    b, _, Wb, Hb = make(gpu_lib, V, W0, H0, use_graph=False)
+    for iters in (37, 1, 16, 5):
+        a.step(iters)
+        b.step(iters)
+        fa, fb = a.objective(), b.objective()
+        assert fa == fb
+        assert torch.equal(Wa, Wb) and torch.equal(Ha, Hb)
+        a.update_w()
+        b.update_w()
+        assert torch.equal(Wa, Wb)
+        a.update_h()
+        b.update_h()
+        assert torch.equal(Ha, Hb)
+    a.close()
+    b.close()
