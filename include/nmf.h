@@ -157,6 +157,51 @@ nmf_status nmf_profile_start(nmf_ctx* ctx, int32_t max_records);
    timed launches (launches_host[NMF_STAGE_COUNT]); either may be NULL. */
 nmf_status nmf_profile_stop(nmf_ctx* ctx, double* ms_host, int32_t* launches_host);
 
+/* ---- Learned warm start -------------------------------------------------
+   A small network maps one column v of V (p values) to a starting column of
+   H (r values): h0 = softplus(M2 relu(M1 v + b1) + b2), M1 hidden x p,
+   M2 r x hidden.  It is trained on columns of converged factorizations
+   (pairs v_j, h_j) with the mean squared error and Adam; at solve time
+   nmf_mlp_predict fills H0 for a new V and the multiplicative updates refine
+   it (the updates only descend, so the start cannot hurt the end point of a
+   monotone run).  Matrix products run in bfloat16 on the matrix cores with
+   float32 accumulation; master weights and Adam moments are float32. */
+typedef struct nmf_mlp nmf_mlp;
+
+/* Create a network for inputs of p features, `hidden` units (a multiple of
+   128), r <= 64 outputs, and batches of at most max_batch columns.
+   M1 (hidden x p), b1 (hidden), M2 (r x hidden), b2 (r): device pointers
+   to the initial float32 weights, copied in. */
+nmf_status nmf_mlp_create(nmf_mlp** out, int32_t p, int32_t hidden, int32_t r,
+                          int64_t max_batch, const float* M1, const float* b1,
+                          const float* M2, const float* b2, void* stream);
+
+/* H0 (r x n, row-major, device) = the network applied to each of the n
+   columns of V (p x n, row stride ldv, device).  Asynchronous. */
+nmf_status nmf_mlp_predict(nmf_mlp* m, const float* V, int64_t n, int64_t ldv,
+                           float* H0);
+
+/* One Adam step (learning rate lr; beta1 0.9, beta2 0.999, eps 1e-8) on the
+   batch of the n columns of V with targets H (r x n, device): loss =
+   mean over the r x n entries of (h0 - h)^2.  loss_host (may be NULL)
+   receives the loss before the step (synchronizes the stream). */
+nmf_status nmf_mlp_train_step(nmf_mlp* m, const float* V, int64_t n,
+                              int64_t ldv, const float* H, float lr,
+                              double* loss_host);
+
+/* Gradients of that loss at the current weights, without updating them:
+   gM1 (hidden x p), gb1 (hidden), gM2 (r x hidden), gb2 (r), device. */
+nmf_status nmf_mlp_grads(nmf_mlp* m, const float* V, int64_t n, int64_t ldv,
+                         const float* H, float* gM1, float* gb1, float* gM2,
+                         float* gb2, double* loss_host);
+
+/* Copy the float32 weights out (device pointers, shapes as in create). */
+nmf_status nmf_mlp_get_params(nmf_mlp* m, float* M1, float* b1, float* M2,
+                              float* b2);
+
+/* Release the network.  NULL is ignored. */
+void nmf_mlp_destroy(nmf_mlp* m);
+
 /* Release the context's workspace.  NULL is ignored. */
 void nmf_destroy(nmf_ctx* ctx);
 

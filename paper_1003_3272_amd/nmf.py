@@ -84,6 +84,19 @@ def load(path: str = LIB_PATH):
     lib.nmf_profile_start.restype = c_int32
     lib.nmf_profile_stop.argtypes = [P, POINTER(c_double), POINTER(c_int32)]
     lib.nmf_profile_stop.restype = c_int32
+    lib.nmf_mlp_create.argtypes = [POINTER(P), c_int32, c_int32, c_int32, c_int64, P, P, P, P, P]
+    lib.nmf_mlp_create.restype = c_int32
+    lib.nmf_mlp_predict.argtypes = [P, P, c_int64, c_int64, P]
+    lib.nmf_mlp_predict.restype = c_int32
+    lib.nmf_mlp_train_step.argtypes = [P, P, c_int64, c_int64, P, ctypes.c_float,
+                                       POINTER(c_double)]
+    lib.nmf_mlp_train_step.restype = c_int32
+    lib.nmf_mlp_grads.argtypes = [P, P, c_int64, c_int64, P, P, P, P, P, POINTER(c_double)]
+    lib.nmf_mlp_grads.restype = c_int32
+    lib.nmf_mlp_get_params.argtypes = [P, P, P, P, P]
+    lib.nmf_mlp_get_params.restype = c_int32
+    lib.nmf_mlp_destroy.argtypes = [P]
+    lib.nmf_mlp_destroy.restype = None
     lib.nmf_destroy.argtypes = [P]
     lib.nmf_destroy.restype = None
     lib.nmf_strerror.argtypes = [c_int32]
@@ -206,6 +219,85 @@ class Nmf:
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """Warm-start network h0 = softplus(M2 relu(M1 v + b1) + b2) on the GPU.
+
+    params: [M1 (hidden x p), b1, M2 (r x hidden), b2] float32 tensors (any
+    device; copied to the GPU).  V arguments are (p, n) float32 CUDA tensors
+    with unit column stride; H arguments are (r, n) contiguous.
+    """
+
+    def __init__(self, params, max_batch, stream=None):
+        import torch
+        lib = load()
+        M1, b1, M2, b2 = (torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
+                          for x in params)
+        self.hidden, self.p = M1.shape
+        self.r = M2.shape[0]
+        self.stream = stream
+        self._m = c_void_p()
+        st = lib.nmf_mlp_create(byref(self._m), self.p, self.hidden, self.r, int(max_batch),
+                                _ptr(M1), _ptr(b1), _ptr(M2), _ptr(b2), _stream_handle(stream))
+        if st != NMF_OK:
+            self._m = c_void_p()
+            raise NmfError(st, "nmf_mlp_create")
+
+    @staticmethod
+    def _check(st, what):
+        if st != NMF_OK:
+            raise NmfError(st, what)
+
+    def predict(self, V, H0=None):
+        import torch
+        n = V.shape[1]
+        if H0 is None:
+            H0 = torch.empty((self.r, n), dtype=torch.float32, device=V.device)
+        self._check(load().nmf_mlp_predict(self._m, _ptr(V), n, V.stride(0), _ptr(H0)),
+                    "nmf_mlp_predict")
+        return H0
+
+    def train_step(self, V, H, lr, want_loss=True):
+        loss = c_double()
+        self._check(load().nmf_mlp_train_step(self._m, _ptr(V), V.shape[1], V.stride(0), _ptr(H),
+                                              float(lr), byref(loss) if want_loss else None),
+                    "nmf_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def grads(self, V, H):
+        import torch
+        dev = V.device
+        g = [torch.empty((self.hidden, self.p), device=dev), torch.empty(self.hidden, device=dev),
+             torch.empty((self.r, self.hidden), device=dev), torch.empty(self.r, device=dev)]
+        loss = c_double()
+        self._check(load().nmf_mlp_grads(self._m, _ptr(V), V.shape[1], V.stride(0), _ptr(H),
+                                         *[_ptr(x) for x in g], byref(loss)), "nmf_mlp_grads")
+        return g, loss.value
+
+    def params(self):
+        import torch
+        out = [torch.empty((self.hidden, self.p), device="cuda"),
+               torch.empty(self.hidden, device="cuda"),
+               torch.empty((self.r, self.hidden), device="cuda"), torch.empty(self.r, device="cuda")]
+        self._check(load().nmf_mlp_get_params(self._m, *[_ptr(x) for x in out]),
+                    "nmf_mlp_get_params")
+        return out
+
+    def close(self):
+        if self._m:
+            load().nmf_mlp_destroy(self._m)
+            self._m = c_void_p()
 
     def __del__(self):
         try:

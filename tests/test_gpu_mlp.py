@@ -1,0 +1,93 @@
+"""GPU parity of the warm-start network against the FP64 network oracle.
+
+The GPU feeds bfloat16 operands to the matrix cores and accumulates in
+float32; the oracle's bf16=True path rounds the same operands and
+accumulates in float64.  Outputs and gradients then differ only by float32
+accumulation (plus rare one-step bf16 rounding differences of an activation
+whose float32 and float64 values straddle a rounding boundary)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as mo
+from synth import generators as g
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(p=300, d=128, r=20, n=700, seed=5):
+    params = g.mlp_init(p, d, r, seed)
+    rng = np.random.default_rng(seed + 1)
+    params[1] = rng.uniform(-0.1, 0.2, size=d).astype(np.float32)
+    params[3] = rng.uniform(-0.2, 0.2, size=r).astype(np.float32)
+    V = rng.uniform(0, 1, size=(p, n)).astype(np.float32)
+    H = rng.exponential(1.0, size=(r, n)).astype(np.float32)
+    return params, V, H
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("p,d,r,n", [(300, 128, 20, 700), (1024, 512, 48, 4096), (64, 256, 64, 100)])
+def test_forward_matches_oracle(gpu_lib, p, d, r, n):
+    from paper_1003_3272_amd import nmf
+    params, V, _ = _case(p, d, r, n)
+    net = nmf.Mlp(params, max_batch=n)
+    H0 = net.predict(torch.from_numpy(V).cuda()).cpu().numpy()
+    Y, _ = mo.forward(params, V.T, bf16=True)
+    assert rel(H0, Y.T) < 1e-3
+    assert np.allclose(H0, Y.T, rtol=5e-3, atol=1e-4)
+    net.close()
+
+
+@pytest.mark.parametrize("p,d,r,n", [(300, 128, 20, 700), (1024, 512, 48, 4096)])
+def test_gradients_match_oracle(gpu_lib, p, d, r, n):
+    from paper_1003_3272_amd import nmf
+    params, V, H = _case(p, d, r, n, seed=7)
+    net = nmf.Mlp(params, max_batch=n)
+    gpu, loss = net.grads(torch.from_numpy(V).cuda(), torch.from_numpy(H).cuda())
+    Y, cache = mo.forward(params, V.T, bf16=True)
+    ref = mo.backward(params, cache, Y, H.T, bf16=True)
+    assert abs(loss - mo.mse(Y, H.T)) <= 1e-4 * mo.mse(Y, H.T)
+    for gg, rr in zip(gpu, ref):
+        assert rel(gg.cpu().numpy(), rr) < 5e-3
+    # against the exact (float64, unrounded) gradients: the bf16 tier's error
+    Y64, cache64 = mo.forward(params, V.T)
+    exact = mo.backward(params, cache64, Y64, H.T)
+    errs = [rel(gg.cpu().numpy(), ee) for gg, ee in zip(gpu, exact)]
+    print("bf16 gradient error vs float64:", ["%.2e" % e for e in errs])
+    assert max(errs) < 5e-2
+    net.close()
+
+
+def test_adam_step_matches_oracle(gpu_lib):
+    from paper_1003_3272_amd import nmf
+    params, V, H = _case(256, 128, 16, 512, seed=9)
+    net = nmf.Mlp(params, max_batch=512)
+    lr = 1e-3
+    loss0 = net.train_step(torch.from_numpy(V).cuda(), torch.from_numpy(H).cuda(), lr)
+    Y, cache = mo.forward(params, V.T, bf16=True)
+    assert abs(loss0 - mo.mse(Y, H.T)) <= 1e-4 * mo.mse(Y, H.T)
+    grads = mo.backward(params, cache, Y, H.T, bf16=True)
+    zeros = [np.zeros_like(x, dtype=np.float64) for x in params]
+    ref, _, _ = mo.adam_step(params, grads, zeros, zeros, 1, lr=lr)
+    for got, want, p0 in zip(net.params(), ref, params):
+        got = got.cpu().numpy()
+        d = np.abs(got - want)
+        assert d.max() <= 2.01 * lr                 # a sign flip of a ~0 gradient
+        assert np.mean(d < 1e-6) > 0.99
+    net.close()
+
+
+def test_training_reduces_loss(gpu_lib):
+    from paper_1003_3272_amd import nmf
+    params, V, _ = _case(256, 128, 16, 1024, seed=11)
+    teacher = g.mlp_init(256, 128, 16, 99)
+    Yt, _ = mo.forward(teacher, V.T)
+    Vd = torch.from_numpy(V).cuda()
+    Hd = torch.from_numpy(Yt.T.astype(np.float32)).contiguous().cuda()
+    net = nmf.Mlp(params, max_batch=1024)
+    losses = [net.train_step(Vd, Hd, 3e-3) for _ in range(150)]
+    assert losses[-1] < 0.3 * losses[0]
+    net.close()
