@@ -91,8 +91,18 @@ __device__ __forceinline__ void gram_reduce_slice(const GramRed& g) {
   for (int64_t e0 = b * groups; e0 < g.elems; e0 += nwg * groups) {
     const int64_t e = e0 + grp;
     float s = 0.f;
-    if (e < g.elems)
-      for (int q = l32; q < g.count; q += 32) s += g.part[(int64_t)q * g.elems + e];
+    if (e < g.elems) {
+      int q = l32;
+      // 8 loads in flight, added in ascending q
+      for (; q + 7 * 32 < g.count; q += 8 * 32) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = g.part[(int64_t)(q + 32 * u) * g.elems + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; q < g.count; q += 32) s += g.part[(int64_t)q * g.elems + e];
+    }
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
     if (e < g.elems && l32 == 0) g.G[e] = s;
@@ -489,12 +499,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
   const int c = lane & 15, g = lane >> 4;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  // grid: x = split (fastest, so the workgroups sharing a k-chunk of the
+  // small operand are dispatched together and land on the same XCD and
+  // its L2), y = M tile, z = N tile
+  const int64_t n0 = (int64_t)blockIdx.z * BN;
   const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t kb = (int64_t)blockIdx.x * kchunk;
   const int64_t ke = (K < kb + kchunk) ? K : kb + kchunk;
   const int nst = (int)((ke - kb) / BKE);
-  gram_reduce_slice(gr);
 
   // source of this lane in each of the wave's L copy instructions: row
   // rr = 8 (wave L + j) + lane / 8 of the stage, slot lane % 8, which holds
@@ -558,20 +570,24 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
     }
   };
 
+  // Stage st lives in buffer st % S.  At the top of iteration st, stages
+  // st .. st + S - 2 have been issued; once this wave's copies of stage st
+  // have landed, one barrier certifies both that every wave's copies of
+  // stage st are in LDS and that every wave has finished computing stage
+  // st - 1, whose buffer is then refilled with stage st + S - 1.
   const int pre = nst < S - 1 ? nst : S - 1;
   for (int st = 0; st < pre; ++st) issue(st);
   for (int st = 0; st < nst; ++st) {
-    if (st + S - 1 < nst) {
-      lds_barrier();  // every wave is done with the buffer about to be refilled
-      issue(st + S - 1);
-    }
     const int later = nst - 1 - st;
-    wait_stage<L, S>(later < S - 1 ? later : S - 1);
-    lds_barrier();  // every wave's copies of this stage have landed
+    wait_stage<L, S>(later < S - 2 ? later : S - 2);
+    lds_barrier();
+    if (st + S - 1 < nst) issue(st + S - 1);
     compute(lds + (st % S) * STAGE);
   }
+  // Gram of the previous update, reduced here so the next kernel can use it
+  gram_reduce_slice(gr);
 
-  float* P = part + (int64_t)blockIdx.z * sp;
+  float* P = part + (int64_t)blockIdx.x * sp;
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -964,10 +980,20 @@ __global__ __launch_bounds__(256) void k_objective(
 
 __global__ __launch_bounds__(256) void k_reduce_f64(const double* __restrict__ part,
                                                     int64_t count, double* __restrict__ out) {
+  // thread t sums part[t], part[t + 256], ... in ascending order (8 loads in
+  // flight), then a fixed tree combines the 256 thread sums
   __shared__ double sh[256];
   const int tid = threadIdx.x;
   double s = 0.0;
-  for (int64_t q = tid; q < count; q += 256) s += part[q];
+  int64_t q = tid;
+  for (; q + 7 * 256 < count; q += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[q + 256 * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; q < count; q += 256) s += part[q];
   sh[tid] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -1320,7 +1346,8 @@ hipError_t launch_nt_dma(const DmaCfg& cfg, bool bf16, const void* X, int64_t ld
                          int64_t kchunk, float* part, int64_t ldp, int64_t sp, const GramRed& gr,
                          hipStream_t st) {
   if (cfg.id < 0 || cfg.id >= kDmaCount) return hipErrorInvalidValue;
-  const dim3 grid = tiles3(M, N, cfg.bm, cfg.bn, splits);
+  const dim3 grid((unsigned)splits, (unsigned)((M + cfg.bm - 1) / cfg.bm),
+                  (unsigned)((N + cfg.bn - 1) / cfg.bn));
   return bf16 ? kDma[cfg.id].bf16(X, ldx, Y, ldy, K, kchunk, part, ldp, sp, gr, grid, st)
               : kDma[cfg.id].f32(X, ldx, Y, ldy, K, kchunk, part, ldp, sp, gr, grid, st);
 }
