@@ -12,6 +12,16 @@ once after the timed region as a sanity check.
 Prints one JSON line: iterations/s, the roofline of the dominant kernel
 (from HIP events recorded around every stage inside the timed region) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Then (unless --no-batch) the batched tier: 512 problems of uneven shape,
+200 iterations each in one persistent launch, against a loop of the
+single-problem solver.  Then (unless --no-warm-start) the time-to-tolerance
+experiment: a stream of
+1024 x 4096 matrices sharing a base dictionary (1024 x 48, Gamma(2, 0.5),
+perturbed per matrix by LogNormal(0, 0.1)); the warm-start network
+(1024 -> 512 -> 48) is trained on solver-converged factors of the first
+matrices and the time to an objective gap f / ||V||^2 <= 1e-4 is measured
+on held-out matrices for a cold FP32 start and for BF16 + warm start.
 """
 import argparse
 import json
@@ -40,6 +50,14 @@ def parse():
     ap.add_argument("--r", type=int, default=64)
     ap.add_argument("--ldv-pad", type=int, default=0,
                     help="extra floats per V row in device memory (row-stride experiment)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-tier run")
+    ap.add_argument("--batch-iters", type=int, default=200)
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the time-to-tolerance experiment")
+    ap.add_argument("--ws-train", type=int, default=800, help="training matrices")
+    ap.add_argument("--ws-test", type=int, default=16, help="held-out matrices timed")
+    ap.add_argument("--ws-epochs", type=int, default=6)
+    ap.add_argument("--ws-target-iters", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the FP64 oracle baseline sample (0 disables)")
     return ap.parse_args()
@@ -65,6 +83,168 @@ def cpu_baseline(V, W0, H0, seconds):
     return {"value": k / el, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{k} FP64 iterations (numpy BLAS) of the same workload from the same "
                       f"start, {el:.1f} s"}
+
+
+def _gen_matrix(args):
+    from threadpoolctl import threadpool_limits
+
+    from synth import generators as gen
+    Wb, m = args
+    with threadpool_limits(1):
+        return gen.warm_start_matrix(Wb, m)[0]
+
+
+def _gen_batch_problem(args):
+    from threadpoolctl import threadpool_limits
+
+    from synth import generators as gen
+    b, (p, n, r) = args
+    with threadpool_limits(1):
+        return gen.batch_problem(b, p, n, r)
+
+
+def batched_experiment(args, log):
+    """512 problems (p ~ U{64..1024}, n ~ U{128..4096}, r ~ U{4..64}),
+    200 iterations each in one persistent launch, after autotuning the tile
+    table on the batch; beside it a loop of the single-problem solver over a
+    sample of the same problems."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from paper_1003_3272_amd import nmf
+    from synth import generators as gen
+
+    shapes = gen.batch_shapes()
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, mp.cpu_count())) as pool:
+        host = pool.map(_gen_batch_problem, list(enumerate(shapes)), chunksize=8)
+    t_gen = time.perf_counter() - t0
+    dev = [tuple(torch.from_numpy(x).cuda() for x in t) for t in host]
+    starts = [(W.clone(), H.clone()) for _, W, H in dev]
+    del host
+    iters = args.batch_iters
+    vbytes = sum(4.0 * p * n for p, n, _ in shapes)
+    flops = sum(4.0 * p * n * r for p, n, r in shapes)
+    with nmf.Batch(dev) as b:
+        ms_tuned = b.tune(trial_iters=5)
+        table = b.table
+        log(f"batched: tuned table {table}, {ms_tuned:.3f} ms/iteration in trials")
+        b.step(iters)          # warm-up launch (also captures the graph)
+        b.check()
+        for (_, W, H), (W0, H0) in zip(dev, starts):
+            W.copy_(W0)
+            H.copy_(H0)
+        b.load()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.step(iters)
+        e1.record()
+        b.check()
+        ms = e0.elapsed_time(e1)
+        f = b.objective()
+    # the single-problem solver, one problem after another, on a sample
+    sample = list(range(0, len(shapes), len(shapes) // 16))[:16]
+    t_loop = 0.0
+    for k in sample:
+        V, _, _ = dev[k]
+        W, H = starts[k][0].clone(), starts[k][1].clone()
+        with nmf.Nmf(V, W, H) as ctx:
+            ctx.step(2)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            ctx.step(iters)
+            torch.cuda.synchronize()
+            t_loop += time.perf_counter() - ta
+    work = lambda ks: sum(shapes[k][0] * shapes[k][1] * shapes[k][2] for k in ks)
+    loop_s_est = t_loop * work(range(len(shapes))) / work(sample)
+    sec = ms / 1e3
+    achieved = 2.0 * vbytes * iters / sec / 1e9
+    return {
+        "workload": "512 problems, p ~ U{64..1024}, n ~ U{128..4096}, r ~ U{4..64} (seed 4000), "
+                    "sparse planted V (seed 100000+b), U(0,1) start (seed 200000+b), fp32",
+        "iterations": iters,
+        "seconds": round(sec, 4),
+        "problem_iters_per_s": round(len(shapes) * iters / sec, 1),
+        "effective_GBps": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "note": "algorithmic bytes: two float32 reads of every V per iteration"},
+        "tflops": round(flops * iters / sec / 1e12, 2),
+        "tile_table": table,
+        "loop_single_solver_s_est": round(loop_s_est, 3),
+        "speedup_vs_loop": round(loop_s_est / sec, 2),
+        "loop_sample": f"{len(sample)} problems (every 32nd), time scaled by p*n*r",
+        "objective_finite": bool(np.all(np.isfinite(f))),
+        "generate_s": round(t_gen, 1),
+    }
+
+
+def warm_start_experiment(args, log):
+    """Time to a 1e-4 objective gap on held-out matrices: FP32 cold start vs
+    BF16 refinement from W-bar and the trained network's H0."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from paper_1003_3272_amd import nmf
+    from paper_1003_3272_amd import warmstart as ws
+    from synth import generators as gen
+
+    t_all = time.perf_counter()
+    Wb = gen.warm_start_base()
+    ids = list(range(args.ws_train)) + list(range(800, 800 + args.ws_test))
+    with mp.get_context("fork").Pool(min(16, mp.cpu_count())) as pool:
+        mats = pool.map(_gen_matrix, [(Wb, m) for m in ids], chunksize=8)
+    t_gen = time.perf_counter() - t_all
+    Vs = [torch.from_numpy(V).cuda() for V in mats]
+    del mats
+    train, test = Vs[:args.ws_train], Vs[args.ws_train:]
+    t0 = time.perf_counter()
+    Wbar = ws.mean_dictionary(train[:16], 48, iters=600, precision="bf16")
+    t_dict = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Hs = ws.fit_targets(train, Wbar, iters=args.ws_target_iters, precision="bf16")
+    t_targets = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net = ws.make_network(gen.mlp_init(1024, 512, 48, 5001), Hs, max_batch=512)
+    losses = ws.train(net, train, Hs, epochs=args.ws_epochs, lr=1e-3, batch=512, decay=0.8,
+                      log=log)
+    t_train = time.perf_counter() - t0
+    del Hs
+    runs = {"fp32_cold": [], "bf16_cold": [], "bf16_wbar": [], "bf16_net": []}
+    for i, V in enumerate(test):
+        m = 800 + i
+        runs["fp32_cold"].append(ws.solve_to_gap(V, "cold", precision="fp32", seed=400000 + m,
+                                                 Wbar=Wbar))
+        runs["bf16_cold"].append(ws.solve_to_gap(V, "cold", precision="bf16", seed=400000 + m,
+                                                 Wbar=Wbar))
+        runs["bf16_wbar"].append(ws.solve_to_gap(V, "wbar", precision="bf16", Wbar=Wbar))
+        runs["bf16_net"].append(ws.solve_to_gap(V, "net", precision="bf16", Wbar=Wbar, net=net))
+        log(f"test {m}: " + ", ".join(f"{k} {v[-1]['seconds']*1e3:.1f} ms / {v[-1]['iters']} it"
+                                      for k, v in runs.items()))
+    net.close()
+    med = {k: {"ms": round(1e3 * float(np.median([x["seconds"] for x in v])), 2),
+               "iters": int(np.median([x["iters"] for x in v])),
+               "converged": int(sum(x["converged"] for x in v)),
+               "gap_max": float(max(x["gap"] for x in v))} for k, v in runs.items()}
+    return {
+        "workload": "1024x4096 fp32 V_m = W_m H_m / max, W_m = W_base(1024x48, Gamma(2,0.5)) "
+                    "* LogNormal(0,0.1), H_m sparse Exp; rank 48; gap f/||V||^2 <= 1e-4, "
+                    "objective checked every 10 iterations",
+        "train_matrices": args.ws_train, "test_matrices": args.ws_test,
+        "network": "1024-512-48 relu/softplus, bf16 products, Adam",
+        "median": med,
+        "speedup_bf16_net_vs_fp32_cold": round(med["fp32_cold"]["ms"] / med["bf16_net"]["ms"], 2),
+        "network_gain_vs_wbar": round(med["bf16_wbar"]["ms"] / med["bf16_net"]["ms"], 2),
+        "train_loss": [round(x, 6) for x in losses],
+        "pipeline_seconds": {"generate": round(t_gen, 1), "dictionary": round(t_dict, 1),
+                             "targets": round(t_targets, 1), "train": round(t_train, 1),
+                             "total": round(time.perf_counter() - t_all, 1)},
+    }
 
 
 def main():
@@ -157,6 +337,15 @@ def main():
         "objective": {"f0": f0, "f_end": f_end,
                       "gap_end": f_end / float(np.sum(V.astype(np.float64) ** 2))},
     }
+    del Vd, Wd, Hd
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = batched_experiment(
+            args, lambda msg: print(msg, file=sys.stderr, flush=True))
+        torch.cuda.empty_cache()
+    if not args.no_warm_start:
+        out["time_to_gap"] = warm_start_experiment(
+            args, lambda msg: print(msg, file=sys.stderr, flush=True))
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(V, W0, H0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -135,6 +135,10 @@ nmf_status nmf_objective(nmf_ctx* ctx, double* f_host);
 nmf_status nmf_solve(nmf_ctx* ctx, int32_t max_iters, int32_t* iters_done_host,
                      double* f_host, double* trace_host, int32_t trace_len);
 
+/* ||V||_F^2 in float64 (computed once by nmf_init); the normalizer of the
+   NMF_TOL_GAP_NORMALIZED rule.  No device work. */
+nmf_status nmf_data_norm2(nmf_ctx* ctx, double* norm2_host);
+
 /* Stages of one iteration, as timed by the profiler below. */
 typedef enum {
   NMF_STAGE_GEMM_VHT = 0,   /* V H^T split-K partials (W numerator)          */
@@ -157,6 +161,15 @@ nmf_status nmf_profile_start(nmf_ctx* ctx, int32_t max_records);
    timed launches (launches_host[NMF_STAGE_COUNT]); either may be NULL. */
 nmf_status nmf_profile_stop(nmf_ctx* ctx, double* ms_host, int32_t* launches_host);
 
+/* Fix the scale gauge of a factorization in place without changing W H:
+   every nonzero column w_k of W (p x r, device) becomes w_k / |w_k|_2 and
+   row k of H (r x n, device) is multiplied by |w_k|_2 (column norms summed
+   in float64).  The factorization V ~ W H is invariant under W D, D^-1 H
+   for positive diagonal D (a property of the model of Sec. 3.1), so this
+   only picks a representative.  Asynchronous on `stream`. */
+nmf_status nmf_normalize_gauge(float* W, int64_t p, int32_t r, float* H,
+                               int64_t n, void* stream);
+
 /* ---- Learned warm start -------------------------------------------------
    A small network maps one column v of V (p values) to a starting column of
    H (r values): h0 = softplus(M2 relu(M1 v + b1) + b2), M1 hidden x p,
@@ -177,23 +190,25 @@ nmf_status nmf_mlp_create(nmf_mlp** out, int32_t p, int32_t hidden, int32_t r,
                           const float* M2, const float* b2, void* stream);
 
 /* H0 (r x n, row-major, device) = the network applied to each of the n
-   columns of V (p x n, row stride ldv, device).  Asynchronous. */
+   columns of V (p x n, row stride ldv, device).  Any n >= 1: wider inputs
+   are processed in chunks of max_batch columns.  Asynchronous. */
 nmf_status nmf_mlp_predict(nmf_mlp* m, const float* V, int64_t n, int64_t ldv,
                            float* H0);
 
 /* One Adam step (learning rate lr; beta1 0.9, beta2 0.999, eps 1e-8) on the
-   batch of the n columns of V with targets H (r x n, device): loss =
+   batch of the n columns of V with targets H (r x n, device, row stride
+   ldh >= n, so a column slice of a wider target matrix can be passed): loss =
    mean over the r x n entries of (h0 - h)^2.  loss_host (may be NULL)
    receives the loss before the step (synchronizes the stream). */
 nmf_status nmf_mlp_train_step(nmf_mlp* m, const float* V, int64_t n,
-                              int64_t ldv, const float* H, float lr,
-                              double* loss_host);
+                              int64_t ldv, const float* H, int64_t ldh,
+                              float lr, double* loss_host);
 
 /* Gradients of that loss at the current weights, without updating them:
    gM1 (hidden x p), gb1 (hidden), gM2 (r x hidden), gb2 (r), device. */
 nmf_status nmf_mlp_grads(nmf_mlp* m, const float* V, int64_t n, int64_t ldv,
-                         const float* H, float* gM1, float* gb1, float* gM2,
-                         float* gb2, double* loss_host);
+                         const float* H, int64_t ldh, float* gM1, float* gb1,
+                         float* gM2, float* gb2, double* loss_host);
 
 /* Copy the float32 weights out (device pointers, shapes as in create). */
 nmf_status nmf_mlp_get_params(nmf_mlp* m, float* M1, float* b1, float* M2,
@@ -201,6 +216,77 @@ nmf_status nmf_mlp_get_params(nmf_mlp* m, float* M1, float* b1, float* M2,
 
 /* Release the network.  NULL is ignored. */
 void nmf_mlp_destroy(nmf_mlp* m);
+
+/* ---- Batched tier ----------------------------------------------------------
+   Many independent problems V_b ~ W_b H_b of uneven p, n and r (r <= 64)
+   advanced together: every call of nmf_batch_step is ONE persistent kernel
+   launch (replayed from a hipGraph) in which workgroups take tiles of all
+   problems from a shared queue.  One iteration of a problem is the W update
+   then the H update of Algorithm 1 (Sec. 3.1), both with the Gram forms of
+   the denominators and the zero-denominator guard of nmf_step, in float32
+   on the matrix cores.  Results are deterministic for a given tile table. */
+typedef struct nmf_batch nmf_batch;
+
+typedef struct {
+  const float* V;   /* p x n, row stride ldv (device); read-only */
+  float* W;         /* p x r (device): start, overwritten by every step */
+  float* H;         /* r x n (device): start, overwritten by every step */
+  int64_t p, n, ldv;
+  int32_t r;        /* 1..64 */
+  int32_t reserved; /* must be 0 */
+} nmf_problem;
+
+/* Tile table: entries 2c and 2c+1 are the phase-W tile rows and phase-H
+   tile columns, in units of 64 (1 or 2), for padded-rank class c
+   (rank padded to 16 (c + 1)); entry 8 is workgroups per compute unit
+   (1 or 2). */
+#define NMF_BATCH_TABLE_LEN 9
+
+/* Copy the problem list (host array of `count` <= 16383 entries), allocate
+   the workspace (padded working factors, Grams, partials) and load W, H.
+   V, W and H stay owned by the caller and must outlive the batch.  V needs
+   only 4-byte alignment (an aligned copy is kept where it lacks 16 bytes
+   or ldv % 4 != 0).  Errors: NMF_EINVAL (null pointer, p, n or r < 1,
+   ldv < n, reserved != 0), NMF_EUNSUPPORTED (r > 64), NMF_ENOMEM. */
+nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs,
+                            int32_t count, void* stream);
+
+/* Reload every problem's W and H from the caller's arrays (after the
+   caller changed them).  Asynchronous. */
+nmf_status nmf_batch_load(nmf_batch* b);
+
+/* `iters` iterations of every problem (one persistent launch), then the
+   caller's W and H are updated.  Asynchronous; a broken schedule is
+   reported by the next nmf_batch_check / nmf_batch_objective. */
+nmf_status nmf_batch_step(nmf_batch* b, int32_t iters);
+
+/* Synchronize the stream; NMF_EDEVICE if a launch since the last check
+   stopped on its wait bound (its results are then not valid). */
+nmf_status nmf_batch_check(nmf_batch* b);
+
+/* f_host[b] = ||V_b - W_b H_b||_F^2 (eq. for the Euclidean objective,
+   float64 accumulation) for every problem; synchronizes.  NMF_ENONFINITE if
+   any value is not finite. */
+nmf_status nmf_batch_objective(nmf_batch* b, double* f_host);
+
+/* Read / install the tile table (NMF_BATCH_TABLE_LEN ints, host). */
+nmf_status nmf_batch_get_table(nmf_batch* b, int32_t* table);
+nmf_status nmf_batch_set_table(nmf_batch* b, const int32_t* table);
+
+/* Autotuner: times trial_iters iterations of this batch for candidate tile
+   tables (coordinate descent over workgroups per CU and each occurring rank
+   class's tile shape), installs the fastest and leaves W, H and the Grams
+   as they were.  best_ms (host, may be NULL) receives its milliseconds per
+   iteration.  Synchronizes. */
+nmf_status nmf_batch_tune(nmf_batch* b, int32_t trial_iters, double* best_ms);
+
+/* Release the batch (not the caller's arrays).  NULL is ignored. */
+void nmf_batch_destroy(nmf_batch* b);
+
+/* Create, step `iters` iterations, write the objectives to f_out (host,
+   count doubles, may be NULL) and destroy. */
+nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count,
+                           int32_t iters, double* f_out, void* stream);
 
 /* Release the context's workspace.  NULL is ignored. */
 void nmf_destroy(nmf_ctx* ctx);

@@ -1,0 +1,1118 @@
+// Batched tier: many independent multiplicative-update NMF problems of
+// uneven p, n and r (r <= 64) advanced together by ONE persistent kernel
+// launch per call (replayed from a hipGraph).
+//
+// One iteration of a problem (Algorithm 1, W update then H update) is two
+// phases of tiles:
+//   phase W, tile t: rows [t*MB, t*MB+MB) of V.  A = V_rows H^T (K = n) on
+//     the matrix cores, then the fused epilogue B = W_rows G_H,
+//     W_rows <- W_rows * A / B (entry kept where B <= 0), and the tile's
+//     partial Gram W_rows^T W_rows;
+//   phase H, tile t: columns [t*NB, t*NB+NB) of V.  S^T = V_cols^T W (K = p),
+//     then D^T = H_cols^T G_W, H_cols <- H_cols * S / D (same guard), and the
+//     tile's partial Gram H_cols H_cols^T.
+// The last tile of a phase to finish (an arrival counter per problem) sums
+// the partial Grams in tile order, so G_W and G_H are deterministic, and then
+// publishes the phase as done.  A phase-W tile of iteration i waits until
+// phase H of iteration i-1 of its problem is done; a phase-H tile waits for
+// phase W of the same iteration (which also orders every read of W and H
+// before the next overwrite).
+//
+// Workgroups of the persistent grid take tiles from one queue in the order
+// (iteration, phase, problem, tile); a tile only waits for tiles earlier in
+// that order, which running workgroups hold, so the schedule cannot
+// deadlock.  Every wait is bounded in time as well: past the bound the
+// kernel raises an error flag, every other wait returns at once and all
+// workgroups leave, so the launch always ends.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/nmf.h"
+#include "nmf_internal.h"
+
+namespace nmfb {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kThreads = 256;
+constexpr int BK = 32;        // reduction slots per LDS stage
+constexpr int PW = BK + 4;    // pitch of k-contiguous LDS rows (phase W)
+constexpr int kMaxNB = 128;
+constexpr int kMaxMB = 128;
+constexpr int kLdsFloats = 2 * BK * (kMaxNB + 16) + 2 * BK * 80;  // 14336 floats
+static_assert(2 * kMaxMB * PW + 2 * 64 * PW <= kLdsFloats, "phase W stage fits");
+static_assert(64 * (kMaxNB + 16) + 64 * 80 <= kLdsFloats, "phase H epilogue fits");
+static_assert(kMaxMB * 68 + 64 * 68 <= kLdsFloats, "phase W epilogue fits");
+
+// A wait longer than this many ticks of the 100 MHz constant clock (2 s)
+// means the schedule is broken: raise the error flag and leave.
+constexpr uint64_t kWaitTicks = 200000000ull;
+
+}  // namespace
+
+// Per-problem descriptor (device copy; see the host builder for meaning).
+struct Prob {
+  const float* V;
+  float* Wp;     // p x rp, pitch rp (working W, padded columns zero)
+  float* Hp;     // rp x ldh (working H, padded rows and columns zero)
+  float* GH;     // rp x rp
+  float* GW;     // rp x rp
+  float* gpart;  // max(tilesW, tilesH) x rp x rp partial Grams
+  float* W;      // caller's W (p x r)
+  float* H;      // caller's H (r x n)
+  int64_t ldv, ldh;
+  int32_t p, n, r, rp;
+  int32_t msw, msh;  // phase W tile rows = 64 msw; phase H tile columns = 64 msh
+  int32_t tilesW, tilesH;
+};
+
+// Counter block, cleared before every launch: [0] queue head, [32] error
+// flag of this launch, then 4 per problem from kCtrBase: W arrivals, W
+// phases done, H arrivals, H phases done.  One more word after the block
+// keeps the error flag across launches until the host reads and clears it.
+constexpr int kCtrErr = 32;
+constexpr int kCtrBase = 64;
+
+namespace {
+
+__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until *c >= target (bounded); the workgroup learns whether
+// the wait succeeded.  Afterwards every wave acquires at agent scope so that
+// its loads see what the producers released.
+__device__ bool wait_geq(const uint32_t* c, uint32_t target, uint32_t* ctr, uint32_t* sticky,
+                         int* s_flag) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    if (ld_acquire(c) < target) {
+      const uint64_t t0 = wall_clock64();
+      while (ld_acquire(c) < target) {
+        if (ld_acquire(ctr + kCtrErr)) {
+          ok = 0;
+          break;
+        }
+        if (wall_clock64() - t0 > kWaitTicks) {
+          __hip_atomic_fetch_or(ctr + kCtrErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(sticky, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    *s_flag = ok;
+  }
+  __syncthreads();
+  const bool ok = *s_flag != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
+// Publish the tile (all of its global writes) and count its arrival; the
+// last arrival of the phase sums the partial Grams and marks the phase done.
+__device__ void finish_tile(const Prob& P, int tiles, uint32_t iter, uint32_t* arr,
+                            uint32_t* done, float* G, int* s_flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old =
+        __hip_atomic_fetch_add(arr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = (old + 1 == (iter + 1) * (uint32_t)tiles);
+  }
+  __syncthreads();
+  if (!*s_flag) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const int rp = P.rp, elems = rp * rp;
+  // thread e sums partials q = 0, 1, ... in order for its elements; the
+  // elements' loads of one q are independent, so they are all in flight
+  constexpr int U = 16;  // 64 * 64 / 256 elements per thread at most
+  float s[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) s[u] = 0.f;
+  for (int q = 0; q < tiles; ++q) {
+    const float* part = P.gpart + (int64_t)q * elems;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + kThreads * u;
+      if (e < elems) s[u] += part[e];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + kThreads * u;
+    if (e < elems) G[e] = s[u];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(done, iter + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 4 consecutive floats of row `row`, columns col..col+3, zero outside
+// [0, rows) x [0, cols) (ld % 4 == 0 and a 16-byte aligned base).
+__device__ __forceinline__ float4 ld4(const float* __restrict__ p, int64_t ld, int64_t row,
+                                      int64_t rows, int64_t col, int64_t cols) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (row >= rows) return v;
+  const float* q = p + row * ld + col;
+  if (col + 3 < cols) return *reinterpret_cast<const float4*>(q);
+  if (col + 0 < cols) v.x = q[0];
+  if (col + 1 < cols) v.y = q[1];
+  if (col + 2 < cols) v.z = q[2];
+  return v;
+}
+
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+__device__ __forceinline__ float4 lds4(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+
+// ---------------------------------------------------------------------------
+// Phase W tile: MB = 64 MS rows, rank padded to RP = 16 NT.  Wave w owns
+// rows [16 MS w, 16 MS (w+1)); each lane reads 4 consecutive k of a row with
+// one 128-bit LDS load and feeds four MFMAs (slot g of MFMA e is k = 4g + e
+// within the 16-k group), for A and B alike.
+// ---------------------------------------------------------------------------
+template <int MS, int NT>
+__device__ void tile_w(const Prob& P, int t, float* lds) {
+  constexpr int MB = 64 * MS, RP = 16 * NT;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, c = lane & 15, g = lane >> 4;
+  const int64_t p0 = (int64_t)t * MB;
+  const int64_t n = P.n, p = P.p;
+  float* Vs = lds;                     // [2][MB][PW]
+  float* Hs = lds + 2 * kMaxMB * PW;   // [2][RP][PW]
+  constexpr int NV = MB * (BK / 4) / kThreads;                  // float4 per thread (V)
+  constexpr int NH = (RP * (BK / 4) + kThreads - 1) / kThreads;  // float4 per thread (H)
+  float4 rv[NV], rh[NH];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
+      rv[u] = ld4(P.V, P.ldv, p0 + row, p, k0 + 4 * q, n);
+    }
+#pragma unroll
+    for (int u = 0; u < NH; ++u) {
+      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
+      rh[u] = (idx < RP * (BK / 4)) ? ld4(P.Hp, P.ldh, row, RP, k0 + 4 * q, n)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
+      st4(&Vs[(buf * kMaxMB + row) * PW + 4 * q], rv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NH; ++u) {
+      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
+      if (idx < RP * (BK / 4)) st4(&Hs[(buf * 64 + row) * PW + 4 * q], rh[u]);
+    }
+  };
+
+  v4f acc[MS][NT];
+#pragma unroll
+  for (int a = 0; a < MS; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int wrow = 16 * MS * wv;
+  const int nch = (int)((n + BK - 1) / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) gload((int64_t)(ch + 1) * BK);
+    const float* vb = Vs + buf * kMaxMB * PW;
+    const float* hb = Hs + buf * 64 * PW;
+#pragma unroll
+    for (int s = 0; s < BK / 16; ++s) {
+      float4 a[MS], b[NT];
+#pragma unroll
+      for (int ms = 0; ms < MS; ++ms) a[ms] = lds4(&vb[(wrow + 16 * ms + c) * PW + 16 * s + 4 * g]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[nt] = lds4(&hb[(16 * nt + c) * PW + 16 * s + 4 * g]);
+#pragma unroll
+      for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          acc[ms][nt] = mfma(a[ms].x, b[nt].x, acc[ms][nt]);
+          acc[ms][nt] = mfma(a[ms].y, b[nt].y, acc[ms][nt]);
+          acc[ms][nt] = mfma(a[ms].z, b[nt].z, acc[ms][nt]);
+          acc[ms][nt] = mfma(a[ms].w, b[nt].w, acc[ms][nt]);
+        }
+    }
+    if (ch + 1 < nch) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: B = W_rows G_H, W <- W * (A / B), partial Gram ----------
+  constexpr int PS = RP + 4;
+  float* Ws = lds;               // [MB][PS]
+  float* Gs = lds + kMaxMB * 68;  // [RP][PS]
+  for (int idx = tid; idx < MB * (RP / 4); idx += kThreads) {
+    const int row = idx / (RP / 4), q = idx % (RP / 4);
+    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p0 + row < p) w = lds4(&P.Wp[(p0 + row) * RP + 4 * q]);
+    st4(&Ws[row * PS + 4 * q], w);
+  }
+  for (int idx = tid; idx < RP * (RP / 4); idx += kThreads) {
+    const int row = idx / (RP / 4), q = idx % (RP / 4);
+    st4(&Gs[row * PS + 4 * q], lds4(&P.GH[row * RP + 4 * q]));
+  }
+  __syncthreads();
+  v4f den[MS][NT];
+#pragma unroll
+  for (int a = 0; a < MS; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) den[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k0 = 0; k0 < RP; k0 += 16) {
+    float4 a[MS], b[NT];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms) a[ms] = lds4(&Ws[(wrow + 16 * ms + c) * PS + k0 + 4 * g]);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = lds4(&Gs[(16 * nt + c) * PS + k0 + 4 * g]);
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        den[ms][nt] = mfma(a[ms].x, b[nt].x, den[ms][nt]);
+        den[ms][nt] = mfma(a[ms].y, b[nt].y, den[ms][nt]);
+        den[ms][nt] = mfma(a[ms].z, b[nt].z, den[ms][nt]);
+        den[ms][nt] = mfma(a[ms].w, b[nt].w, den[ms][nt]);
+      }
+  }
+  float wn[MS][NT][4];
+#pragma unroll
+  for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = wrow + 16 * ms + 4 * g + v, col = 16 * nt + c;
+        const float w = Ws[lr * PS + col], d = den[ms][nt][v];
+        wn[ms][nt][v] = (d > 0.f) ? w * (acc[ms][nt][v] / d) : w;
+      }
+  // the wave's own rows only (its reads above are done)
+#pragma unroll
+  for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ws[(wrow + 16 * ms + 4 * g + v) * PS + 16 * nt + c] = wn[ms][nt][v];
+  __syncthreads();
+  for (int idx = tid; idx < MB * (RP / 4); idx += kThreads) {
+    const int row = idx / (RP / 4), q = idx % (RP / 4);
+    if (p0 + row < p) st4(&P.Wp[(p0 + row) * RP + 4 * q], lds4(&Ws[row * PS + 4 * q]));
+  }
+  // partial Gram C[i][j] = sum_m Wn[m][i] Wn[m][j] over the tile's rows
+  float* gp = P.gpart + (int64_t)t * RP * RP;
+  for (int st = wv; st < NT * NT; st += 4) {
+    const int it = st / NT, jt = st % NT;
+    v4f cg = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+    for (int m0 = 0; m0 < MB; m0 += 4)
+      cg = mfma(Ws[(m0 + g) * PS + 16 * it + c], Ws[(m0 + g) * PS + 16 * jt + c], cg);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gp[(16 * it + 4 * g + v) * RP + 16 * jt + c] = cg[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase H tile: NB = 64 MS columns of V, rank RP = 16 NT.  The reduction
+// runs down the rows of V (k = row index), so operands are read from LDS one
+// float per lane (row k = 4 s + g, 16 consecutive columns per lane group);
+// pitches are chosen so the four groups fall in distinct banks.
+// ---------------------------------------------------------------------------
+template <int MS, int NT>
+__device__ void tile_h(const Prob& P, int t, float* lds) {
+  constexpr int NB = 64 * MS, RP = 16 * NT;
+  constexpr int PV = NB + 16;
+  constexpr int PR = (RP == 48) ? 80 : RP + 16;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, c = lane & 15, g = lane >> 4;
+  const int64_t j0 = (int64_t)t * NB;
+  const int64_t n = P.n, p = P.p;
+  float* Vs = lds;                          // [2][BK][PV]
+  float* Ws = lds + 2 * BK * (kMaxNB + 16);  // [2][BK][PR]
+  constexpr int NV = BK * (NB / 4) / kThreads;
+  constexpr int NW = (BK * (RP / 4) + kThreads - 1) / kThreads;
+  float4 rv[NV], rw[NW];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int idx = tid + kThreads * u, row = idx / (NB / 4), q = idx % (NB / 4);
+      rv[u] = ld4(P.V, P.ldv, k0 + row, p, j0 + 4 * q, n);
+    }
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
+      rw[u] = (idx < BK * (RP / 4)) ? ld4(P.Wp, RP, k0 + row, p, 4 * q, RP)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int idx = tid + kThreads * u, row = idx / (NB / 4), q = idx % (NB / 4);
+      st4(&Vs[(buf * BK + row) * PV + 4 * q], rv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
+      if (idx < BK * (RP / 4)) st4(&Ws[(buf * BK + row) * PR + 4 * q], rw[u]);
+    }
+  };
+
+  v4f acc[MS][NT];
+#pragma unroll
+  for (int a = 0; a < MS; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int wcol = 16 * MS * wv;
+  const int nch = (int)((p + BK - 1) / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) gload((int64_t)(ch + 1) * BK);
+    const float* vb = Vs + buf * BK * PV;
+    const float* wb = Ws + buf * BK * PR;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      float a[MS], b[NT];
+#pragma unroll
+      for (int ms = 0; ms < MS; ++ms) a[ms] = vb[(kk + g) * PV + wcol + 16 * ms + c];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[nt] = wb[(kk + g) * PR + 16 * nt + c];
+#pragma unroll
+      for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[ms][nt] = mfma(a[ms], b[nt], acc[ms][nt]);
+    }
+    if (ch + 1 < nch) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: D^T = H_cols^T G_W, H <- H * (S / D), partial Gram ------
+  float* Hs = lds;                     // [RP][PV]
+  float* Gs = lds + 64 * (kMaxNB + 16);  // [RP][PR]
+  for (int idx = tid; idx < RP * (NB / 4); idx += kThreads) {
+    const int row = idx / (NB / 4), q = idx % (NB / 4);
+    st4(&Hs[row * PV + 4 * q], ld4(P.Hp, P.ldh, row, RP, j0 + 4 * q, n));
+  }
+  for (int idx = tid; idx < RP * (RP / 4); idx += kThreads) {
+    const int row = idx / (RP / 4), q = idx % (RP / 4);
+    st4(&Gs[row * PR + 4 * q], lds4(&P.GW[row * RP + 4 * q]));
+  }
+  __syncthreads();
+  v4f den[MS][NT];
+#pragma unroll
+  for (int a = 0; a < MS; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) den[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int k0 = 0; k0 < RP; k0 += 4) {
+    float a[MS], b[NT];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms) a[ms] = Hs[(k0 + g) * PV + wcol + 16 * ms + c];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = Gs[(k0 + g) * PR + 16 * nt + c];
+#pragma unroll
+    for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) den[ms][nt] = mfma(a[ms], b[nt], den[ms][nt]);
+  }
+  float hn[MS][NT][4];
+#pragma unroll
+  for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = wcol + 16 * ms + 4 * g + v, k = 16 * nt + c;
+        const float h = Hs[k * PV + m], d = den[ms][nt][v];
+        hn[ms][nt][v] = (d > 0.f) ? h * (acc[ms][nt][v] / d) : h;
+      }
+  // the wave's own columns only (its reads above are done)
+#pragma unroll
+  for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Hs[(16 * nt + c) * PV + wcol + 16 * ms + 4 * g + v] = hn[ms][nt][v];
+  __syncthreads();
+  // columns >= n hold zeros (masked loads, zero numerators), and the rows
+  // of Hp are padded to a multiple of 4 columns, so whole float4s are stored
+  for (int idx = tid; idx < RP * (NB / 4); idx += kThreads) {
+    const int row = idx / (NB / 4), q = idx % (NB / 4);
+    if (j0 + 4 * q < n) st4(&P.Hp[row * P.ldh + j0 + 4 * q], lds4(&Hs[row * PV + 4 * q]));
+  }
+  // partial Gram C[i][j] = sum_m Hn[i][m] Hn[j][m] over the tile's columns
+  float* gp = P.gpart + (int64_t)t * RP * RP;
+  for (int st = wv; st < NT * NT; st += 4) {
+    const int it = st / NT, jt = st % NT;
+    v4f cg = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int m0 = 0; m0 < NB; m0 += 16) {
+      const float4 a = lds4(&Hs[(16 * it + c) * PV + m0 + 4 * g]);
+      const float4 b = lds4(&Hs[(16 * jt + c) * PV + m0 + 4 * g]);
+      cg = mfma(a.x, b.x, cg);
+      cg = mfma(a.y, b.y, cg);
+      cg = mfma(a.z, b.z, cg);
+      cg = mfma(a.w, b.w, cg);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gp[(16 * it + 4 * g + v) * RP + 16 * jt + c] = cg[v];
+  }
+}
+
+#define NMFB_CASES(X) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 1) X(2, 2) X(2, 3) X(2, 4)
+
+// The persistent kernel.  sched holds one iteration's tiles, each coded as
+// problem << 17 | phase << 16 | tile; entry e of iteration i is queue slot
+// i * per_iter + e.
+__global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __restrict__ probs,
+                                                               const uint32_t* __restrict__ sched,
+                                                               uint32_t per_iter, uint32_t total,
+                                                               uint32_t* __restrict__ ctr,
+                                                               uint32_t* __restrict__ sticky) {
+  __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
+  __shared__ uint32_t s_slot;
+  __shared__ int s_flag;
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_slot = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t slot = s_slot;
+    __syncthreads();
+    if (slot >= total) break;
+    const uint32_t iter = slot / per_iter;
+    const uint32_t code = __builtin_amdgcn_readfirstlane(sched[slot % per_iter]);
+    const int b = (int)(code >> 17), phase = (int)((code >> 16) & 1), t = (int)(code & 0xffff);
+    const Prob& P = probs[b];  // uniform: read with scalar loads, never copied
+    uint32_t* pc = ctr + kCtrBase + 4 * b;
+    if (phase == 0) {
+      if (!wait_geq(pc + 3, iter, ctr, sticky, &s_flag)) break;  // H phase of iteration - 1
+      switch (P.msw * 8 + P.rp / 16) {
+#define CASE_W(MS, NT) \
+  case MS * 8 + NT:    \
+    tile_w<MS, NT>(P, t, lds); \
+    break;
+        NMFB_CASES(CASE_W)
+#undef CASE_W
+        default: break;
+      }
+      finish_tile(P, P.tilesW, iter, pc + 0, pc + 1, P.GW, &s_flag);
+    } else {
+      if (!wait_geq(pc + 1, iter + 1, ctr, sticky, &s_flag)) break;  // W phase of this iteration
+      switch (P.msh * 8 + P.rp / 16) {
+#define CASE_H(MS, NT) \
+  case MS * 8 + NT:    \
+    tile_h<MS, NT>(P, t, lds); \
+    break;
+        NMFB_CASES(CASE_H)
+#undef CASE_H
+        default: break;
+      }
+      finish_tile(P, P.tilesH, iter, pc + 2, pc + 3, P.GH, &s_flag);
+    }
+    __syncthreads();
+  }
+}
+
+// Set-up and copy kernels (grid.y = problem).
+__global__ __launch_bounds__(256) void k_batch_load(const Prob* __restrict__ probs) {
+  const Prob P = probs[blockIdx.y];
+  const int64_t nw = (int64_t)P.p * P.rp, nh = (int64_t)P.rp * P.ldh;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < nw + nh; e += (int64_t)gridDim.x * 256) {
+    if (e < nw) {
+      const int64_t i = e / P.rp;
+      const int k = (int)(e % P.rp);
+      P.Wp[e] = (k < P.r) ? P.W[i * P.r + k] : 0.f;
+    } else {
+      const int64_t f = e - nw;
+      const int k = (int)(f / P.ldh);
+      const int64_t j = f % P.ldh;
+      P.Hp[f] = (k < P.r && j < P.n) ? P.H[(int64_t)k * P.n + j] : 0.f;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_store(const Prob* __restrict__ probs) {
+  const Prob P = probs[blockIdx.y];
+  const int64_t nw = (int64_t)P.p * P.r, nh = (int64_t)P.r * P.n;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < nw + nh; e += (int64_t)gridDim.x * 256) {
+    if (e < nw) {
+      const int64_t i = e / P.r;
+      const int k = (int)(e % P.r);
+      P.W[e] = P.Wp[i * P.rp + k];
+    } else {
+      const int64_t f = e - nw;
+      const int k = (int)(f / P.n);
+      const int64_t j = f % P.n;
+      P.H[f] = P.Hp[(int64_t)k * P.ldh + j];
+    }
+  }
+}
+
+// G_H = H H^T of the loaded H (one workgroup per problem and 16 x 16 block
+// of G; a lane pair of 16 x 16 threads forms each entry by a float32
+// running sum over the columns in order).
+__global__ __launch_bounds__(256) void k_batch_gram_h(const Prob* __restrict__ probs) {
+  const Prob P = probs[blockIdx.y];
+  const int nb = P.rp / 16;
+  if ((int)blockIdx.x >= nb * nb) return;
+  const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;
+  const int i = 16 * bi + (threadIdx.x >> 4), k = 16 * bj + (threadIdx.x & 15);
+  const float* hi = P.Hp + (int64_t)i * P.ldh;
+  const float* hk = P.Hp + (int64_t)k * P.ldh;
+  float s = 0.f;
+  for (int64_t j = 0; j < P.n; ++j) s = fmaf(hi[j], hk[j], s);
+  P.GH[i * P.rp + k] = s;
+}
+
+// Objective tiles: 64 x 64 blocks of V - W H of every problem, float64
+// accumulation of float64 products of the float32 factors; one double per
+// tile, summed per problem in tile order by k_batch_obj_sum.
+__global__ __launch_bounds__(256) void k_batch_objective(const Prob* __restrict__ probs,
+                                                         const int4* __restrict__ tiles,
+                                                         double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) float WsT[64 * 64];
+  __shared__ __attribute__((aligned(16))) float Hs[64 * 64];
+  __shared__ double red[4];
+  const int4 td = tiles[blockIdx.x];
+  const Prob P = probs[td.x];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int64_t i0 = (int64_t)td.y * 64, j0 = (int64_t)td.z * 64;
+  const int rp = P.rp;
+  for (int idx = tid; idx < 64 * rp; idx += 256) {
+    const int ii = idx / rp, kk = idx % rp;
+    WsT[kk * 64 + ii] = (i0 + ii < P.p) ? P.Wp[(i0 + ii) * rp + kk] : 0.f;
+  }
+  for (int idx = tid; idx < rp * 64; idx += 256) {
+    const int kk = idx / 64, jj = idx % 64;
+    Hs[idx] = (j0 + jj < P.n) ? P.Hp[(int64_t)kk * P.ldh + j0 + jj] : 0.f;
+  }
+  __syncthreads();
+  double s[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s[a][b] = 0.0;
+  for (int kk = 0; kk < rp; ++kk) {
+    const float4 w = lds4(&WsT[kk * 64 + 4 * ty]);
+    const float4 h = lds4(&Hs[kk * 64 + 4 * tx]);
+    const double wd[4] = {(double)w.x, (double)w.y, (double)w.z, (double)w.w};
+    const double hd[4] = {(double)h.x, (double)h.y, (double)h.z, (double)h.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) s[a][b] = fma(wd[a], hd[b], s[a][b]);
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t row = i0 + 4 * ty + a, col = j0 + 4 * tx;
+    const float4 v = ld4(P.V, P.ldv, row, P.p, col, P.n);
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (row < P.p && col + b < P.n) {
+        const double e = (double)vv[b] - s[a][b];
+        acc = fma(e, e, acc);
+      }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_batch_obj_sum(const double* __restrict__ part,
+                                                       const int64_t* __restrict__ first,
+                                                       double* __restrict__ f) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t lo = first[b], hi = first[b + 1];
+  double s = 0.0;
+  for (int64_t q = lo + tid; q < hi; q += 256) s += part[q];
+  sh[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) f[b] = sh[0];
+}
+
+__global__ void k_batch_fill(uint32_t* __restrict__ p, int64_t count) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+inline int64_t up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+}  // namespace nmfb
+
+using nmfb::Prob;
+
+struct nmf_batch {
+  int count = 0;
+  hipStream_t st = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = 0, cus = 0;
+  std::vector<nmf_problem> user;
+  std::vector<Prob> host;       // descriptors (device pointers)
+  std::vector<float*> vcopy;    // aligned copies of V where the caller's is not
+  char* arena = nullptr;        // factors, Grams, partials (one allocation)
+  size_t factor_bytes = 0;      // leading part of the arena that tuning saves
+  Prob* dprobs = nullptr;
+  uint32_t* ctr = nullptr;
+  int64_t nctr = 0;
+  uint32_t* sched = nullptr;
+  uint32_t per_iter = 0;
+  int4* obj_tiles = nullptr;
+  int64_t nobj = 0;
+  int64_t* obj_first = nullptr;
+  double* obj_part = nullptr;
+  double* fdev = nullptr;
+  double* hostbuf = nullptr;
+  int32_t table[NMF_BATCH_TABLE_LEN] = {0};
+  hipGraphExec_t graph = nullptr;
+  int32_t graph_iters = 0;
+  uint32_t* hosterr = nullptr;
+};
+
+namespace nmfb {
+namespace {
+
+#define BTRY_HIP(x)                                \
+  do {                                             \
+    if ((x) != hipSuccess) return NMF_EDEVICE;     \
+  } while (0)
+#define BTRY(x)                          \
+  do {                                   \
+    const nmf_status s_ = (x);           \
+    if (s_ != NMF_OK) return s_;         \
+  } while (0)
+
+// Default tile table (rows of phase-W tiles and columns of phase-H tiles in
+// units of 64, per padded-rank class 16 / 32 / 48 / 64; workgroups per CU).
+void default_table(int32_t* t) {
+  const int32_t d[NMF_BATCH_TABLE_LEN] = {1, 1, 1, 1, 1, 1, 1, 1, 2};
+  std::memcpy(t, d, sizeof(d));
+}
+
+bool table_ok(const int32_t* t) {
+  for (int q = 0; q < 8; ++q)
+    if (t[q] != 1 && t[q] != 2) return false;
+  return t[8] >= 1 && t[8] <= 2;
+}
+
+// Apply the table to the descriptors and rebuild the schedule.
+nmf_status plan(nmf_batch* b) {
+  std::vector<uint32_t> w, h;
+  // problems in decreasing order of work, so that large tiles start early
+  std::vector<int> order(b->count);
+  for (int i = 0; i < b->count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const Prob &a = b->host[x], &c = b->host[y];
+    return (int64_t)a.p * a.n * a.rp > (int64_t)c.p * c.n * c.rp;
+  });
+  for (int i = 0; i < b->count; ++i) {
+    Prob& P = b->host[i];
+    const int cls = P.rp / 16 - 1;
+    P.msw = b->table[2 * cls];
+    P.msh = b->table[2 * cls + 1];
+    P.tilesW = (int32_t)((P.p + 64 * P.msw - 1) / (64 * P.msw));
+    P.tilesH = (int32_t)((P.n + 64 * P.msh - 1) / (64 * P.msh));
+    if (P.tilesW > 65535 || P.tilesH > 65535) return NMF_EUNSUPPORTED;
+  }
+  for (int i : order) {
+    const Prob& P = b->host[i];
+    for (int t = 0; t < P.tilesW; ++t) w.push_back(((uint32_t)i << 17) | (uint32_t)t);
+  }
+  for (int i : order) {
+    const Prob& P = b->host[i];
+    for (int t = 0; t < P.tilesH; ++t) h.push_back(((uint32_t)i << 17) | (1u << 16) | (uint32_t)t);
+  }
+  w.insert(w.end(), h.begin(), h.end());
+  if (b->sched) (void)hipFree(b->sched);
+  b->sched = nullptr;
+  BTRY_HIP(hipMalloc(&b->sched, w.size() * sizeof(uint32_t)));
+  BTRY_HIP(hipMemcpyAsync(b->sched, w.data(), w.size() * sizeof(uint32_t), hipMemcpyHostToDevice, b->st));
+  BTRY_HIP(hipMemcpyAsync(b->dprobs, b->host.data(), b->host.size() * sizeof(Prob),
+                          hipMemcpyHostToDevice, b->st));
+  BTRY_HIP(hipStreamSynchronize(b->st));
+  b->per_iter = (uint32_t)w.size();
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_iters = 0;
+  return NMF_OK;
+}
+
+nmf_status enqueue_steps(nmf_batch* b, int32_t iters, hipStream_t s) {
+  const uint64_t total = (uint64_t)iters * b->per_iter;
+  if (total >= 0xffffffffull) return NMF_EUNSUPPORTED;
+  hipLaunchKernelGGL(k_batch_fill, dim3((unsigned)std::min<int64_t>(64, (b->nctr + 255) / 256)),
+                     dim3(256), 0, s, b->ctr, b->nctr);
+  BTRY_HIP(hipGetLastError());
+  const unsigned grid = (unsigned)(b->cus * b->table[8]);
+  hipLaunchKernelGGL(k_batch_persistent, dim3(grid), dim3(kThreads), 0, s, b->dprobs, b->sched,
+                     b->per_iter, (uint32_t)total, b->ctr, b->ctr + b->nctr);
+  BTRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_batch_store, dim3(64, (unsigned)b->count), dim3(256), 0, s, b->dprobs);
+  BTRY_HIP(hipGetLastError());
+  return NMF_OK;
+}
+
+nmf_status capture(nmf_batch* b, int32_t iters) {
+  if (!b->cap_stream) BTRY_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  BTRY_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  const nmf_status s = enqueue_steps(b, iters, b->cap_stream);
+  const hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+  if (s != NMF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess || !graph) return NMF_EDEVICE;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return NMF_EDEVICE;
+  b->graph_iters = iters;
+  return NMF_OK;
+}
+
+// Synchronize; NMF_EDEVICE if a launch since the last check hit the wait
+// bound (the flag is then cleared).
+nmf_status check_error(nmf_batch* b) {
+  BTRY_HIP(hipMemcpyAsync(b->hosterr, b->ctr + b->nctr, 4, hipMemcpyDeviceToHost, b->st));
+  BTRY_HIP(hipStreamSynchronize(b->st));
+  if (!*b->hosterr) return NMF_OK;
+  hipLaunchKernelGGL(k_batch_fill, dim3(1), dim3(256), 0, b->st, b->ctr + b->nctr, (int64_t)1);
+  BTRY_HIP(hipStreamSynchronize(b->st));
+  return NMF_EDEVICE;
+}
+
+}  // namespace
+}  // namespace nmfb
+
+extern "C" {
+
+nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t count,
+                            void* stream) {
+  using namespace nmfb;
+  if (!out) return NMF_EINVAL;
+  *out = nullptr;
+  if (!probs || count < 1 || count > 16383) return NMF_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = probs[i];
+    if (!q.V || !q.W || !q.H || q.p < 1 || q.n < 1 || q.r < 1 || q.ldv < q.n) return NMF_EINVAL;
+    if (q.p > INT32_MAX || q.n > INT32_MAX || q.reserved != 0) return NMF_EINVAL;
+    if (reinterpret_cast<uintptr_t>(q.V) % 4 || reinterpret_cast<uintptr_t>(q.W) % 4 ||
+        reinterpret_cast<uintptr_t>(q.H) % 4)
+      return NMF_EINVAL;
+    if (q.r > 64) return NMF_EUNSUPPORTED;
+  }
+  nmf_batch* b = new (std::nothrow) nmf_batch();
+  if (!b) return NMF_ENOMEM;
+  b->count = count;
+  b->st = reinterpret_cast<hipStream_t>(stream);
+  b->user.assign(probs, probs + count);
+  b->host.resize(count);
+  default_table(b->table);
+  nmf_status s = NMF_OK;
+  auto fail = [&](nmf_status e) {
+    nmf_batch_destroy(b);
+    return e;
+  };
+  if (hipGetDevice(&b->device) != hipSuccess) return fail(NMF_EDEVICE);
+  if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) !=
+      hipSuccess)
+    return fail(NMF_EDEVICE);
+  // arena: Wp and Hp of all problems, then G_H of all problems (together
+  // the state that tuning saves and restores), then G_W and partials
+  size_t off = 0;
+  std::vector<size_t> oW(count), oH(count), oGH(count), oGW(count), oP(count);
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = probs[i];
+    const int rp = (int)up(q.r, 16);
+    oW[i] = off;
+    off += up(q.p * rp * 4, 256);
+    oH[i] = off;
+    off += up((int64_t)rp * up(q.n, 4) * 4, 256);
+  }
+  for (int i = 0; i < count; ++i) {
+    const int64_t rp = up(probs[i].r, 16);
+    oGH[i] = off;
+    off += up(rp * rp * 4, 256);
+  }
+  b->factor_bytes = off;  // W, H and G_H: the state carried between calls
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = probs[i];
+    const int64_t rp = up(q.r, 16);
+    oGW[i] = off;
+    off += up(rp * rp * 4, 256);
+    // partial Grams for the smallest tiles (64 rows / columns)
+    const int64_t tiles = std::max((q.p + 63) / 64, (q.n + 63) / 64);
+    oP[i] = off;
+    off += up(tiles * rp * rp * 4, 256);
+  }
+  if (hipMalloc(&b->arena, off) != hipSuccess) return fail(NMF_ENOMEM);
+  if (hipMemsetAsync(b->arena, 0, off, b->st) != hipSuccess) return fail(NMF_EDEVICE);
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = probs[i];
+    Prob& P = b->host[i];
+    P.V = q.V;
+    P.ldv = q.ldv;
+    if (reinterpret_cast<uintptr_t>(q.V) % 16 || q.ldv % 4) {
+      // the tile loaders read 16-byte vectors: keep an aligned copy
+      float* cp = nullptr;
+      const int64_t ld = up(q.n, 4);
+      if (hipMalloc(&cp, q.p * ld * 4) != hipSuccess) return fail(NMF_ENOMEM);
+      b->vcopy.push_back(cp);
+      if (nmfk::launch_copy_pad(q.V, q.ldv, q.p, q.n, cp, ld, b->st) != hipSuccess)
+        return fail(NMF_EDEVICE);
+      P.V = cp;
+      P.ldv = ld;
+    }
+    P.p = (int32_t)q.p;
+    P.n = (int32_t)q.n;
+    P.r = q.r;
+    P.rp = (int32_t)up(q.r, 16);
+    P.ldh = up(q.n, 4);
+    P.Wp = reinterpret_cast<float*>(b->arena + oW[i]);
+    P.Hp = reinterpret_cast<float*>(b->arena + oH[i]);
+    P.GH = reinterpret_cast<float*>(b->arena + oGH[i]);
+    P.GW = reinterpret_cast<float*>(b->arena + oGW[i]);
+    P.gpart = reinterpret_cast<float*>(b->arena + oP[i]);
+    P.W = q.W;
+    P.H = q.H;
+  }
+  b->nctr = kCtrBase + 4 * (int64_t)count;
+  if (hipMalloc(&b->dprobs, count * sizeof(Prob)) != hipSuccess) return fail(NMF_ENOMEM);
+  if (hipMalloc(&b->ctr, (b->nctr + 1) * 4) != hipSuccess) return fail(NMF_ENOMEM);
+  if (hipMemsetAsync(b->ctr, 0, (b->nctr + 1) * 4, b->st) != hipSuccess) return fail(NMF_EDEVICE);
+  if (hipHostMalloc(&b->hostbuf, count * sizeof(double)) != hipSuccess) return fail(NMF_ENOMEM);
+  if (hipHostMalloc(&b->hosterr, sizeof(uint32_t)) != hipSuccess) return fail(NMF_ENOMEM);
+  // objective tiles
+  std::vector<int4> ot;
+  std::vector<int64_t> first(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    first[i] = (int64_t)ot.size();
+    const nmf_problem& q = probs[i];
+    for (int64_t a = 0; a < (q.p + 63) / 64; ++a)
+      for (int64_t c = 0; c < (q.n + 63) / 64; ++c) ot.push_back(make_int4(i, (int)a, (int)c, 0));
+  }
+  first[count] = (int64_t)ot.size();
+  b->nobj = (int64_t)ot.size();
+  if (b->nobj > INT32_MAX) return fail(NMF_EUNSUPPORTED);
+  if (hipMalloc(&b->obj_tiles, ot.size() * sizeof(int4)) != hipSuccess ||
+      hipMalloc(&b->obj_first, first.size() * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&b->obj_part, ot.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&b->fdev, count * sizeof(double)) != hipSuccess)
+    return fail(NMF_ENOMEM);
+  if (hipMemcpyAsync(b->obj_tiles, ot.data(), ot.size() * sizeof(int4), hipMemcpyHostToDevice,
+                     b->st) != hipSuccess ||
+      hipMemcpyAsync(b->obj_first, first.data(), first.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice, b->st) != hipSuccess)
+    return fail(NMF_EDEVICE);
+  s = plan(b);
+  if (s != NMF_OK) return fail(s);
+  s = nmf_batch_load(b);
+  if (s != NMF_OK) return fail(s);
+  if (hipStreamSynchronize(b->st) != hipSuccess) return fail(NMF_EDEVICE);
+  *out = b;
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_load(nmf_batch* b) {
+  using namespace nmfb;
+  if (!b) return NMF_EINVAL;
+  hipLaunchKernelGGL(k_batch_load, dim3(64, (unsigned)b->count), dim3(256), 0, b->st, b->dprobs);
+  BTRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_batch_gram_h, dim3(16, (unsigned)b->count), dim3(256), 0, b->st, b->dprobs);
+  BTRY_HIP(hipGetLastError());
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_step(nmf_batch* b, int32_t iters) {
+  using namespace nmfb;
+  if (!b || iters < 0) return NMF_EINVAL;
+  if (iters == 0) return NMF_OK;
+  if (!b->graph || b->graph_iters != iters) BTRY(capture(b, iters));
+  BTRY_HIP(hipGraphLaunch(b->graph, b->st));
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_check(nmf_batch* b) {
+  if (!b) return NMF_EINVAL;
+  return nmfb::check_error(b);
+}
+
+nmf_status nmf_batch_objective(nmf_batch* b, double* f_host) {
+  using namespace nmfb;
+  if (!b || !f_host) return NMF_EINVAL;
+  hipLaunchKernelGGL(k_batch_objective, dim3((unsigned)b->nobj), dim3(256), 0, b->st, b->dprobs,
+                     b->obj_tiles, b->obj_part);
+  BTRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_batch_obj_sum, dim3((unsigned)b->count), dim3(256), 0, b->st, b->obj_part,
+                     b->obj_first, b->fdev);
+  BTRY_HIP(hipGetLastError());
+  BTRY_HIP(hipMemcpyAsync(b->hostbuf, b->fdev, b->count * sizeof(double), hipMemcpyDeviceToHost,
+                          b->st));
+  BTRY(check_error(b));
+  for (int i = 0; i < b->count; ++i) {
+    if (!std::isfinite(b->hostbuf[i])) return NMF_ENONFINITE;
+    f_host[i] = b->hostbuf[i];
+  }
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_get_table(nmf_batch* b, int32_t* table) {
+  if (!b || !table) return NMF_EINVAL;
+  std::memcpy(table, b->table, sizeof(b->table));
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_set_table(nmf_batch* b, const int32_t* table) {
+  using namespace nmfb;
+  if (!b || !table || !table_ok(table)) return NMF_EINVAL;
+  BTRY_HIP(hipStreamSynchronize(b->st));
+  std::memcpy(b->table, table, sizeof(b->table));
+  return plan(b);
+}
+
+nmf_status nmf_batch_tune(nmf_batch* b, int32_t trial_iters, double* best_ms) {
+  using namespace nmfb;
+  if (!b || trial_iters < 1) return NMF_EINVAL;
+  BTRY_HIP(hipStreamSynchronize(b->st));
+  // save the factors and G_H (restored at the end, so tuning leaves the
+  // state exactly as it found it)
+  char* save = nullptr;
+  BTRY_HIP(hipMalloc(&save, b->factor_bytes));
+  BTRY_HIP(hipMemcpyAsync(save, b->arena, b->factor_bytes, hipMemcpyDeviceToDevice, b->st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  nmf_status s = NMF_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) s = NMF_EDEVICE;
+  auto timed = [&](const int32_t* t, float* ms) -> nmf_status {
+    std::memcpy(b->table, t, sizeof(b->table));
+    BTRY(plan(b));
+    BTRY(enqueue_steps(b, 1, b->st));  // warm-up
+    BTRY_HIP(hipEventRecord(e0, b->st));
+    BTRY(enqueue_steps(b, trial_iters, b->st));
+    BTRY_HIP(hipEventRecord(e1, b->st));
+    BTRY_HIP(hipEventSynchronize(e1));
+    BTRY_HIP(hipEventElapsedTime(ms, e0, e1));
+    return check_error(b);
+  };
+  // which rank classes occur
+  bool used[4] = {false, false, false, false};
+  for (const Prob& P : b->host) used[P.rp / 16 - 1] = true;
+  int32_t best[NMF_BATCH_TABLE_LEN];
+  std::memcpy(best, b->table, sizeof(best));
+  float tbest = 0.f;
+  if (s == NMF_OK) s = timed(best, &tbest);
+  // coordinate descent over the workgroups per CU, then each class's
+  // (phase W rows, phase H columns)
+  for (int w = 1; w <= 2 && s == NMF_OK; ++w) {
+    if (w == best[8]) continue;
+    int32_t cand[NMF_BATCH_TABLE_LEN];
+    std::memcpy(cand, best, sizeof(cand));
+    cand[8] = w;
+    float tm = 0.f;
+    s = timed(cand, &tm);
+    if (s == NMF_OK && tm < 0.98f * tbest) {
+      tbest = tm;
+      std::memcpy(best, cand, sizeof(best));
+    }
+  }
+  for (int cls = 0; cls < 4 && s == NMF_OK; ++cls) {
+    if (!used[cls]) continue;
+    for (int mw = 1; mw <= 2 && s == NMF_OK; ++mw)
+      for (int mh = 1; mh <= 2 && s == NMF_OK; ++mh) {
+        if (mw == best[2 * cls] && mh == best[2 * cls + 1]) continue;
+        int32_t cand[NMF_BATCH_TABLE_LEN];
+        std::memcpy(cand, best, sizeof(cand));
+        cand[2 * cls] = mw;
+        cand[2 * cls + 1] = mh;
+        float tm = 0.f;
+        s = timed(cand, &tm);
+        if (s == NMF_OK && tm < 0.98f * tbest) {
+          tbest = tm;
+          std::memcpy(best, cand, sizeof(best));
+        }
+      }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  std::memcpy(b->table, best, sizeof(best));
+  nmf_status s2 = plan(b);
+  if (s == NMF_OK) s = s2;
+  // restore the state (factors and G_H) and the caller's copies
+  if (hipMemcpyAsync(b->arena, save, b->factor_bytes, hipMemcpyDeviceToDevice, b->st) !=
+      hipSuccess)
+    s = NMF_EDEVICE;
+  hipLaunchKernelGGL(k_batch_store, dim3(64, (unsigned)b->count), dim3(256), 0, b->st, b->dprobs);
+  if (hipStreamSynchronize(b->st) != hipSuccess) s = NMF_EDEVICE;
+  (void)hipFree(save);
+  if (best_ms) *best_ms = (double)tbest / trial_iters;
+  return s;
+}
+
+void nmf_batch_destroy(nmf_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->st);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (float* p : b->vcopy) (void)hipFree(p);
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->dprobs) (void)hipFree(b->dprobs);
+  if (b->ctr) (void)hipFree(b->ctr);
+  if (b->sched) (void)hipFree(b->sched);
+  if (b->obj_tiles) (void)hipFree(b->obj_tiles);
+  if (b->obj_first) (void)hipFree(b->obj_first);
+  if (b->obj_part) (void)hipFree(b->obj_part);
+  if (b->fdev) (void)hipFree(b->fdev);
+  if (b->hostbuf) (void)hipHostFree(b->hostbuf);
+  if (b->hosterr) (void)hipHostFree(b->hosterr);
+  delete b;
+}
+
+nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count, int32_t iters,
+                           double* f_out, void* stream) {
+  if (iters < 0) return NMF_EINVAL;
+  nmf_batch* b = nullptr;
+  nmf_status s = nmf_batch_create(&b, probs, count, stream);
+  if (s != NMF_OK) return s;
+  s = nmf_batch_step(b, iters);
+  if (s == NMF_OK && f_out) s = nmf_batch_objective(b, f_out);
+  if (s == NMF_OK && !f_out) s = nmf_batch_check(b);
+  nmf_batch_destroy(b);
+  return s;
+}
+
+}  // extern "C"

@@ -148,6 +148,10 @@ hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t rows,
 hipError_t launch_transpose_f32(const float* src, int64_t lds, int64_t rows,
                                 int64_t cols, float* dst, int64_t ldd,
                                 hipStream_t st);
+// Scale every nonzero column of W (p x r) to unit norm and the matching row
+// of H (r x n) by that norm; norms: r floats of scratch.
+hipError_t launch_gauge(float* W, int64_t p, int r, float* H, int64_t n, float* norms,
+                        hipStream_t st);
 // flag |= 1 if some V entry is negative or non-finite.
 hipError_t launch_validate(const float* V, int64_t ldv, int64_t p, int64_t n,
                            uint32_t* flag, hipStream_t st);

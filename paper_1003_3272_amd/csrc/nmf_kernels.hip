@@ -1110,6 +1110,43 @@ __global__ void k_uniform(float* __restrict__ dst, int64_t rows, int64_t cols, i
   }
 }
 
+// Gauge fixing of a factorization (W H is unchanged): w_k <- w_k / |w_k|,
+// h_k <- h_k |w_k| for every column k of W with a nonzero norm.  One
+// workgroup per column sums the squares in float64 in a fixed order.
+__global__ __launch_bounds__(256) void k_col_norms(const float* __restrict__ W, int64_t p, int r,
+                                                   float* __restrict__ norms) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int64_t i = tid; i < p; i += 256) {
+    const double w = W[i * r + k];
+    s += w * w;
+  }
+  sh[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) norms[k] = (float)sqrt(sh[0]);
+}
+
+__global__ void k_apply_gauge(float* __restrict__ W, int64_t p, int r, float* __restrict__ H,
+                              int64_t n, const float* __restrict__ norms) {
+  const int64_t tw = p * r, total = tw + (int64_t)r * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (idx < tw) {
+      const float nk = norms[idx % r];
+      if (nk > 0.f) W[idx] = W[idx] / nk;
+    } else {
+      const int64_t j = idx - tw;
+      const float nk = norms[j / n];
+      if (nk > 0.f) H[j] = H[j] * nk;
+    }
+  }
+}
+
 inline unsigned grid1d(int64_t total, int threads, int64_t cap = 65536) {
   int64_t b = (total + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -1470,6 +1507,14 @@ hipError_t launch_validate(const float* V, int64_t ldv, int64_t p, int64_t n, ui
                            hipStream_t st) {
   hipLaunchKernelGGL(k_validate, dim3(grid1d(p * n, 256, 16384)), dim3(256), 0, st, V, ldv, p, n,
                      flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauge(float* W, int64_t p, int r, float* H, int64_t n, float* norms,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_col_norms, dim3((unsigned)r), dim3(256), 0, st, W, p, r, norms);
+  hipLaunchKernelGGL(k_apply_gauge, dim3(grid1d(p * r + (int64_t)r * n, 256)), dim3(256), 0, st, W,
+                     p, r, H, n, norms);
   return hipGetLastError();
 }
 

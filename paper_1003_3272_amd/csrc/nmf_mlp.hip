@@ -509,29 +509,36 @@ nmf_status nmf_mlp_create(nmf_mlp** out, int32_t p, int32_t hidden, int32_t r, i
 }
 
 nmf_status nmf_mlp_predict(nmf_mlp* m, const float* V, int64_t n, int64_t ldv, float* H0) {
-  nmf_status s = check_batch(m, V, n, ldv);
-  if (s != NMF_OK) return s;
+  if (!m || n < 1 || ldv < n) return NMF_EINVAL;
   if (!H0 || reinterpret_cast<uintptr_t>(H0) % 4 != 0) return NMF_EINVAL;
-  if (n != m->Bp) {
-    s = zero_batch(m);
+  // column chunks of at most max_batch examples; H0 keeps row stride n
+  for (int64_t a = 0; a < n; a += m->nmax) {
+    const int64_t nb = std::min<int64_t>(m->nmax, n - a);
+    nmf_status s = check_batch(m, V + a, nb, ldv);
+    if (s != NMF_OK) return s;
+    if (nb != m->Bp) {
+      s = zero_batch(m);
+      if (s != NMF_OK) return s;
+    }
+    s = load_batch(m, V + a, nb, ldv);
+    if (s == NMF_OK) s = forward(m, nb, H0 + a, n, nullptr, 0);
     if (s != NMF_OK) return s;
   }
-  s = load_batch(m, V, n, ldv);
-  if (s != NMF_OK) return s;
-  return forward(m, n, H0, n, nullptr, 0);
+  return NMF_OK;
 }
 
 static nmf_status train_or_grad(nmf_mlp* m, const float* V, int64_t n, int64_t ldv,
-                                const float* T, float lr, double* loss_host, float* const* grads) {
+                                const float* T, int64_t ldt, float lr, double* loss_host,
+                                float* const* grads) {
   nmf_status s = check_batch(m, V, n, ldv);
   if (s != NMF_OK) return s;
-  if (!T || reinterpret_cast<uintptr_t>(T) % 4 != 0) return NMF_EINVAL;
+  if (!T || reinterpret_cast<uintptr_t>(T) % 4 != 0 || ldt < n) return NMF_EINVAL;
   if (n != m->Bp) {
     s = zero_batch(m);
     if (s != NMF_OK) return s;
   }
   s = load_batch(m, V, n, ldv);
-  if (s == NMF_OK) s = forward(m, n, nullptr, 0, T, n);
+  if (s == NMF_OK) s = forward(m, n, nullptr, 0, T, ldt);
   Plan pg1{}, pg2{};
   if (s == NMF_OK) s = backward(m, &pg1, &pg2);
   if (s == NMF_OK) s = adam_all(m, pg1, pg2, lr, grads, m->gtmp);
@@ -546,16 +553,17 @@ static nmf_status train_or_grad(nmf_mlp* m, const float* V, int64_t n, int64_t l
 }
 
 nmf_status nmf_mlp_train_step(nmf_mlp* m, const float* V, int64_t n, int64_t ldv, const float* H,
-                              float lr, double* loss_host) {
+                              int64_t ldh, float lr, double* loss_host) {
   if (!(lr > 0.f) || !std::isfinite(lr)) return NMF_EINVAL;
-  return train_or_grad(m, V, n, ldv, H, lr, loss_host, nullptr);
+  return train_or_grad(m, V, n, ldv, H, ldh, lr, loss_host, nullptr);
 }
 
 nmf_status nmf_mlp_grads(nmf_mlp* m, const float* V, int64_t n, int64_t ldv, const float* H,
-                         float* gM1, float* gb1, float* gM2, float* gb2, double* loss_host) {
+                         int64_t ldh, float* gM1, float* gb1, float* gM2, float* gb2,
+                         double* loss_host) {
   if (!gM1 || !gb1 || !gM2 || !gb2) return NMF_EINVAL;
   float* const grads[4] = {gM1, gb1, gM2, gb2};
-  return train_or_grad(m, V, n, ldv, H, 0.f, loss_host, grads);
+  return train_or_grad(m, V, n, ldv, H, ldh, 0.f, loss_host, grads);
 }
 
 nmf_status nmf_mlp_get_params(nmf_mlp* m, float* M1, float* b1, float* M2, float* b2) {

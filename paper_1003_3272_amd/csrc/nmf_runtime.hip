@@ -608,6 +608,12 @@ nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double*
   return NMF_ENOTCONVERGED;
 }
 
+nmf_status nmf_data_norm2(nmf_ctx* c, double* norm2_host) {
+  if (!c || !norm2_host) return NMF_EINVAL;
+  *norm2_host = c->nv2;
+  return NMF_OK;
+}
+
 nmf_status nmf_profile_start(nmf_ctx* c, int32_t max_records) {
   if (!c || max_records < 1) return NMF_EINVAL;
   TRY_HIP(hipStreamSynchronize(c->st));
@@ -667,6 +673,22 @@ const char* nmf_strerror(nmf_status s) {
     case NMF_EUNSUPPORTED: return "unsupported rank, size or option";
   }
   return "unknown status";
+}
+
+nmf_status nmf_normalize_gauge(float* W, int64_t p, int32_t r, float* H, int64_t n,
+                               void* stream) {
+  if (!W || !H || p < 1 || n < 1 || r < 1 || r > NMF_MAX_RANK) return NMF_EINVAL;
+  if (reinterpret_cast<uintptr_t>(W) % 4 != 0 || reinterpret_cast<uintptr_t>(H) % 4 != 0)
+    return NMF_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* norms = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&norms), sizeof(float) * r, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return NMF_ENOMEM;
+  }
+  const hipError_t e = launch_gauge(W, p, r, H, n, norms, st);
+  (void)hipFreeAsync(norms, st);
+  return e == hipSuccess ? NMF_OK : NMF_EDEVICE;
 }
 
 int32_t nmf_version(void) { return 100; }

@@ -44,6 +44,15 @@ class NmfOptions(ctypes.Structure):
     ]
 
 
+class NmfProblem(ctypes.Structure):
+    """One problem of the batched tier (device pointers, row-major)."""
+    _fields_ = [("V", c_void_p), ("W", c_void_p), ("H", c_void_p), ("p", c_int64),
+                ("n", c_int64), ("ldv", c_int64), ("r", c_int32), ("reserved", c_int32)]
+
+
+BATCH_TABLE_LEN = 9
+
+
 class NmfError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -80,18 +89,23 @@ def load(path: str = LIB_PATH):
     lib.nmf_solve.argtypes = [P, c_int32, POINTER(c_int32), POINTER(c_double),
                               POINTER(c_double), c_int32]
     lib.nmf_solve.restype = c_int32
+    lib.nmf_data_norm2.argtypes = [P, POINTER(c_double)]
+    lib.nmf_data_norm2.restype = c_int32
     lib.nmf_profile_start.argtypes = [P, c_int32]
     lib.nmf_profile_start.restype = c_int32
     lib.nmf_profile_stop.argtypes = [P, POINTER(c_double), POINTER(c_int32)]
     lib.nmf_profile_stop.restype = c_int32
+    lib.nmf_normalize_gauge.argtypes = [P, c_int64, c_int32, P, c_int64, P]
+    lib.nmf_normalize_gauge.restype = c_int32
     lib.nmf_mlp_create.argtypes = [POINTER(P), c_int32, c_int32, c_int32, c_int64, P, P, P, P, P]
     lib.nmf_mlp_create.restype = c_int32
     lib.nmf_mlp_predict.argtypes = [P, P, c_int64, c_int64, P]
     lib.nmf_mlp_predict.restype = c_int32
-    lib.nmf_mlp_train_step.argtypes = [P, P, c_int64, c_int64, P, ctypes.c_float,
+    lib.nmf_mlp_train_step.argtypes = [P, P, c_int64, c_int64, P, c_int64, ctypes.c_float,
                                        POINTER(c_double)]
     lib.nmf_mlp_train_step.restype = c_int32
-    lib.nmf_mlp_grads.argtypes = [P, P, c_int64, c_int64, P, P, P, P, P, POINTER(c_double)]
+    lib.nmf_mlp_grads.argtypes = [P, P, c_int64, c_int64, P, c_int64, P, P, P, P,
+                                  POINTER(c_double)]
     lib.nmf_mlp_grads.restype = c_int32
     lib.nmf_mlp_get_params.argtypes = [P, P, P, P, P]
     lib.nmf_mlp_get_params.restype = c_int32
@@ -99,6 +113,25 @@ def load(path: str = LIB_PATH):
     lib.nmf_mlp_destroy.restype = None
     lib.nmf_destroy.argtypes = [P]
     lib.nmf_destroy.restype = None
+    lib.nmf_batch_create.argtypes = [POINTER(P), POINTER(NmfProblem), c_int32, P]
+    lib.nmf_batch_create.restype = c_int32
+    for name in ("nmf_batch_load", "nmf_batch_check"):
+        getattr(lib, name).argtypes = [P]
+        getattr(lib, name).restype = c_int32
+    lib.nmf_batch_step.argtypes = [P, c_int32]
+    lib.nmf_batch_step.restype = c_int32
+    lib.nmf_batch_objective.argtypes = [P, POINTER(c_double)]
+    lib.nmf_batch_objective.restype = c_int32
+    lib.nmf_batch_get_table.argtypes = [P, POINTER(c_int32)]
+    lib.nmf_batch_get_table.restype = c_int32
+    lib.nmf_batch_set_table.argtypes = [P, POINTER(c_int32)]
+    lib.nmf_batch_set_table.restype = c_int32
+    lib.nmf_batch_tune.argtypes = [P, c_int32, POINTER(c_double)]
+    lib.nmf_batch_tune.restype = c_int32
+    lib.nmf_batch_destroy.argtypes = [P]
+    lib.nmf_batch_destroy.restype = None
+    lib.nmf_batch_solve.argtypes = [POINTER(NmfProblem), c_int32, c_int32, POINTER(c_double), P]
+    lib.nmf_batch_solve.restype = c_int32
     lib.nmf_strerror.argtypes = [c_int32]
     lib.nmf_strerror.restype = ctypes.c_char_p
     lib.nmf_version.argtypes = []
@@ -123,6 +156,14 @@ def options(precision="fp32", tol_kind="rel_change", tol=1e-9, check_every=1,
     o.seed = int(seed)
     o.use_graph = 1 if use_graph else 0
     return o
+
+
+def normalize_gauge(W, H, stream=None):
+    """In place: unit-norm columns of W (p x r), rows of H (r x n) rescaled."""
+    st = load().nmf_normalize_gauge(c_void_p(W.data_ptr()), W.shape[0], W.shape[1],
+                                    c_void_p(H.data_ptr()), H.shape[1], _stream_handle(stream))
+    if st != NMF_OK:
+        raise NmfError(st, "nmf_normalize_gauge")
 
 
 def _stream_handle(stream):
@@ -199,6 +240,12 @@ class Nmf:
             ntr = min(trace_len, 1 + (it.value + ce - 1) // ce)
         return st == NMF_OK, it.value, f.value, [buf[i] for i in range(ntr)]
 
+    def data_norm2(self) -> float:
+        """||V||_F^2 (float64), as used by the gap stopping rule."""
+        v = c_double()
+        self._check(load().nmf_data_norm2(self._ctx, byref(v)), "nmf_data_norm2")
+        return v.value
+
     def profile_start(self, max_records: int):
         self._check(load().nmf_profile_start(self._ctx, int(max_records)), "nmf_profile_start")
 
@@ -231,12 +278,24 @@ def _ptr(t):
     return c_void_p(t.data_ptr())
 
 
+def _check_rows(V, H):
+    """Training batches: float32 device matrices with unit column stride and
+    the same number of columns."""
+    import torch
+    for x, name in ((V, "V"), (H, "H")):
+        if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 2 or x.stride(1) != 1:
+            raise ValueError(f"{name} must be a 2-D float32 device tensor with unit column stride")
+    if V.shape[1] != H.shape[1]:
+        raise ValueError("V and H must have the same number of columns")
+
+
 class Mlp:
     """Warm-start network h0 = softplus(M2 relu(M1 v + b1) + b2) on the GPU.
 
     params: [M1 (hidden x p), b1, M2 (r x hidden), b2] float32 tensors (any
-    device; copied to the GPU).  V arguments are (p, n) float32 CUDA tensors
-    with unit column stride; H arguments are (r, n) contiguous.
+    device; copied to the GPU).  V and training-target H arguments are (p, n)
+    and (r, n) float32 CUDA tensors with unit column stride (column slices of
+    wider matrices are accepted); predict's output H0 is contiguous.
     """
 
     def __init__(self, params, max_batch, stream=None):
@@ -270,8 +329,10 @@ class Mlp:
 
     def train_step(self, V, H, lr, want_loss=True):
         loss = c_double()
+        _check_rows(V, H)
         self._check(load().nmf_mlp_train_step(self._m, _ptr(V), V.shape[1], V.stride(0), _ptr(H),
-                                              float(lr), byref(loss) if want_loss else None),
+                                              H.stride(0), float(lr),
+                                              byref(loss) if want_loss else None),
                     "nmf_mlp_train_step")
         return loss.value if want_loss else None
 
@@ -281,8 +342,10 @@ class Mlp:
         g = [torch.empty((self.hidden, self.p), device=dev), torch.empty(self.hidden, device=dev),
              torch.empty((self.r, self.hidden), device=dev), torch.empty(self.r, device=dev)]
         loss = c_double()
+        _check_rows(V, H)
         self._check(load().nmf_mlp_grads(self._m, _ptr(V), V.shape[1], V.stride(0), _ptr(H),
-                                         *[_ptr(x) for x in g], byref(loss)), "nmf_mlp_grads")
+                                         H.stride(0), *[_ptr(x) for x in g], byref(loss)),
+                    "nmf_mlp_grads")
         return g, loss.value
 
     def params(self):
@@ -298,6 +361,97 @@ class Mlp:
         if self._m:
             load().nmf_mlp_destroy(self._m)
             self._m = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _problem_list(problems):
+    """NmfProblem array from (V, W, H) float32 device tensors: V (p, n) with
+    unit column stride, W (p, r) and H (r, n) contiguous."""
+    import torch
+    arr = (NmfProblem * len(problems))()
+    for i, (V, W, H) in enumerate(problems):
+        for x, name in ((V, "V"), (W, "W"), (H, "H")):
+            if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 2:
+                raise ValueError(f"problem {i}: {name} must be a 2-D float32 device tensor")
+        if V.stride(1) != 1 or not W.is_contiguous() or not H.is_contiguous():
+            raise ValueError(f"problem {i}: V needs unit column stride, W and H contiguous")
+        p, n = V.shape
+        r = W.shape[1]
+        if W.shape[0] != p or H.shape != (r, n):
+            raise ValueError(f"problem {i}: shapes V {tuple(V.shape)}, W {tuple(W.shape)}, "
+                             f"H {tuple(H.shape)} do not match")
+        arr[i] = NmfProblem(V.data_ptr(), W.data_ptr(), H.data_ptr(), p, n, V.stride(0), r, 0)
+    return arr
+
+
+class Batch:
+    """Batched tier: many independent problems (V_b, W_b, H_b) advanced by one
+    persistent kernel launch per step call.  W_b and H_b are read at
+    creation (and by load()) and overwritten in place after every step."""
+
+    def __init__(self, problems, stream=None):
+        self._refs = [tuple(t) for t in problems]
+        self.count = len(self._refs)
+        arr = _problem_list(self._refs)
+        self._b = c_void_p()
+        st = load().nmf_batch_create(byref(self._b), arr, self.count, _stream_handle(stream))
+        if st != NMF_OK:
+            self._b = c_void_p()
+            raise NmfError(st, "nmf_batch_create")
+
+    @staticmethod
+    def _check(st, what):
+        if st != NMF_OK:
+            raise NmfError(st, what)
+
+    def step(self, iters=1):
+        self._check(load().nmf_batch_step(self._b, int(iters)), "nmf_batch_step")
+
+    def load(self):
+        self._check(load().nmf_batch_load(self._b), "nmf_batch_load")
+
+    def check(self):
+        self._check(load().nmf_batch_check(self._b), "nmf_batch_check")
+
+    def objective(self):
+        import numpy as np
+        out = (c_double * self.count)()
+        self._check(load().nmf_batch_objective(self._b, out), "nmf_batch_objective")
+        return np.array(out[:], dtype=np.float64)
+
+    @property
+    def table(self):
+        t = (c_int32 * BATCH_TABLE_LEN)()
+        self._check(load().nmf_batch_get_table(self._b, t), "nmf_batch_get_table")
+        return list(t)
+
+    @table.setter
+    def table(self, values):
+        t = (c_int32 * BATCH_TABLE_LEN)(*[int(v) for v in values])
+        self._check(load().nmf_batch_set_table(self._b, t), "nmf_batch_set_table")
+
+    def tune(self, trial_iters=5):
+        """Autotune the tile table on this batch; returns ms per iteration of
+        the table it installs."""
+        ms = c_double()
+        self._check(load().nmf_batch_tune(self._b, int(trial_iters), byref(ms)), "nmf_batch_tune")
+        return ms.value
+
+    def close(self):
+        if self._b:
+            load().nmf_batch_destroy(self._b)
+            self._b = c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

@@ -1,0 +1,143 @@
+"""Learned warm start for the multiplicative NMF solver: data pipeline,
+training and time-to-tolerance runs.
+
+Every numerical step runs in the HIP library:
+- solves: nmf.Nmf (multiplicative updates, FP32 or BF16 tier);
+- gauge fixing: nmf.normalize_gauge;
+- the network: nmf.Mlp (bf16 matrix-core products, Adam).
+This module only schedules those calls and moves tensors between them.
+
+Pipeline (for a stream of matrices V_m that share a dictionary):
+1. mean dictionary W-bar: a joint factorization of the column-wise
+   concatenation of a few training matrices, columns scaled to unit norm;
+2. targets: each training matrix is factored starting from W = W-bar, and
+   the result is put in the unit-norm-column gauge, so that its H columns h_j
+   are expressed in (nearly) W-bar's basis;
+3. the network is trained on the pairs (v_j, h_j);
+4. a new matrix starts from W0 = W-bar and H0 = network(V) and is refined by
+   the multiplicative updates (which never increase the objective).
+"""
+from __future__ import annotations
+
+import time
+
+from . import nmf
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def mean_dictionary(Vs, r, iters, precision="bf16", seed=1):
+    """Unit-norm-column W-bar (p x r) from a joint factorization of the
+    column-wise concatenation of the matrices in Vs."""
+    import torch
+    Vcat = torch.cat(list(Vs), dim=1).contiguous()
+    p, n = Vcat.shape
+    W = torch.empty((p, r), dtype=torch.float32, device=Vcat.device)
+    H = torch.empty((r, n), dtype=torch.float32, device=Vcat.device)
+    with nmf.Nmf(Vcat, W, H, precision=precision, seed=seed) as ctx:
+        ctx.step(iters)
+    nmf.normalize_gauge(W, H)
+    _sync()
+    del Vcat, H
+    return W
+
+
+def fit_targets(Vs, Wbar, iters, precision="bf16"):
+    """For each V: factor from (W-bar, constant H) for `iters` iterations and
+    return H in the unit-norm-column gauge (r x n tensors)."""
+    import torch
+    out = []
+    r = Wbar.shape[1]
+    for V in Vs:
+        W = Wbar.clone()
+        H = torch.full((r, V.shape[1]), 1.0 / r, dtype=torch.float32, device=V.device)
+        with nmf.Nmf(V, W, H, precision=precision) as ctx:
+            ctx.step(iters)
+        nmf.normalize_gauge(W, H)
+        out.append(H)
+    _sync()
+    return out
+
+
+def output_bias(Hs):
+    """Starting output bias: softplus^-1 of the mean target entry, so that the
+    untrained network already predicts the targets' mean.  (With a zero bias
+    the first Adam steps push the softplus deep into its flat negative range,
+    where its slope, and with it every gradient, all but vanishes.)"""
+    import math
+    tot = sum(float(H.sum()) for H in Hs)
+    cnt = sum(H.numel() for H in Hs)
+    mean = max(tot / cnt, 1e-6)
+    return math.log(math.expm1(mean))
+
+
+def make_network(params, Hs, max_batch):
+    """nmf.Mlp from initial [M1, b1, M2, b2] (numpy or torch) with b2 set by
+    output_bias(Hs)."""
+    import numpy as np
+    M1, b1, M2, b2 = (np.array(x, dtype=np.float32, copy=True) for x in params)
+    b2[:] = output_bias(Hs)
+    return nmf.Mlp([M1, b1, M2, b2], max_batch=max_batch)
+
+
+def train(net, Vs, Hs, epochs, lr, batch=512, decay=0.9, seed=0, log=None):
+    """Adam epochs over the (V_m, H_m) pairs in minibatches of `batch`
+    columns (column slices, no copies); matrices in a seeded random order
+    each epoch, the learning rate scaled by `decay` after each epoch.
+    Returns the mean minibatch loss of each epoch."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    losses = []
+    rate = lr
+    for ep in range(epochs):
+        order = rng.permutation(len(Vs))
+        tot, cnt = 0.0, 0
+        for m in order:
+            V, H = Vs[m], Hs[m]
+            for a in range(0, V.shape[1], batch):
+                tot += net.train_step(V[:, a:a + batch], H[:, a:a + batch], rate, want_loss=True)
+                cnt += 1
+        losses.append(tot / cnt)
+        if log:
+            log(f"epoch {ep}: loss {losses[-1]:.4e} lr {rate:.2e}")
+        rate *= decay
+    return losses
+
+
+def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters=20000,
+                 net=None, Wbar=None, seed=None):
+    """Time to reach f / ||V||_F^2 <= tol from a given start (V already on
+    the device).  start: "cold" (device U(0,1) draw keyed by `seed`),
+    "wbar" (W-bar and a constant H), or "net" (W-bar and H0 = net(V)).
+    The clock covers everything after V is resident: the start, context
+    set-up (casts, copies), every iteration and every objective check.
+    Returns a dict with seconds, iterations, final gap and convergence."""
+    import torch
+    p, n = V.shape
+    r = Wbar.shape[1] if Wbar is not None else net.r
+    _sync()
+    t0 = time.perf_counter()
+    if start == "cold":
+        if not seed:
+            raise ValueError("a cold start needs a nonzero seed")
+        W = torch.empty((p, r), dtype=torch.float32, device=V.device)
+        H = torch.empty((r, n), dtype=torch.float32, device=V.device)
+        ctx = nmf.Nmf(V, W, H, precision=precision, tol_kind="gap", tol=tol,
+                      check_every=check_every, seed=seed)
+    else:
+        W = Wbar.clone()
+        if start == "net":
+            H = net.predict(V)
+        else:
+            H = torch.full((r, n), 1.0 / r, dtype=torch.float32, device=V.device)
+        ctx = nmf.Nmf(V, W, H, precision=precision, tol_kind="gap", tol=tol,
+                      check_every=check_every)
+    conv, iters, f, _ = ctx.solve(max_iters)
+    _sync()
+    seconds = time.perf_counter() - t0
+    gap = f / ctx.data_norm2()
+    ctx.close()
+    return {"seconds": seconds, "iters": iters, "gap": gap, "converged": bool(conv)}

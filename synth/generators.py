@@ -13,7 +13,8 @@ Recipes (sizes are the workloads the library is measured on):
                    V = W* H* / max(W* H*)               (image-like, in [0,1])
   uniform_init     W0 ~ U(0,1)^{p x r}, H0 ~ U(0,1)^{r x n}, exact zeros
                    redrawn (the start is drawn on the open interval (0,1)).
-  batch_shapes     512 triples p ~ U{64..1024}, n ~ U{128..4096}, r ~ U{4..64}
+  batch_shapes     512 triples p ~ U{64..1024}, n ~ U{128..4096}, r ~ U{4..64};
+                   problem b: sparse_planted seed 100000 + b, start seed 200000 + b
   warm_start       W_base ~ Gamma(2, 0.5)^{1024 x 48}; matrix m uses
                    W_m = W_base * LogNormal(0, 0.1), H_m sparse Exp,
                    V_m = W_m H_m / max.
@@ -83,6 +84,14 @@ def batch_shapes(count=512, seed=4000):
         r = int(rng.integers(4, 64, endpoint=True))
         out.append((p, n, r))
     return out
+
+
+def batch_problem(b, p, n, r, dtype=np.float32):
+    """Problem b of the batched workload: sparse planted V (seed 100000 + b)
+    and a U(0,1) start (seed 200000 + b); returns (V, W0, H0)."""
+    V, _, _ = sparse_planted(p, n, r, seed=100000 + b, dtype=dtype)
+    W0, H0 = uniform_init(p, n, r, seed=200000 + b, dtype=dtype)
+    return V, W0, H0
 
 
 def warm_start_base(p=1024, r=48, seed=5000):

@@ -116,3 +116,57 @@ def test_null_context_calls():
     assert lib.nmf_objective(None, ctypes.byref(f)) == nmf.NMF_EINVAL
     assert lib.nmf_solve(None, 1, ctypes.byref(it), ctypes.byref(f), None, 0) == nmf.NMF_EINVAL
     lib.nmf_destroy(None)  # must not crash
+
+
+def test_problem_struct_layout_matches_header():
+    # three pointers, three int64, two int32 -> 56 bytes
+    assert ctypes.sizeof(nmf.NmfProblem) == 56
+    assert nmf.NmfProblem.p.offset == 24
+    assert nmf.NmfProblem.r.offset == 48
+
+
+def _batch_create(count=2, out=True, **kw):
+    lib = nmf.load()
+    arr = (nmf.NmfProblem * max(count, 1))()
+    for i in range(max(count, 1)):
+        f = dict(V=FAKE, W=FAKE, H=FAKE, p=8, n=8, ldv=8, r=2, reserved=0)
+        if i == count - 1:
+            f.update(kw)
+        arr[i] = nmf.NmfProblem(f["V"], f["W"], f["H"], f["p"], f["n"], f["ldv"], f["r"],
+                                f["reserved"])
+    b = ctypes.c_void_p(123)
+    st = lib.nmf_batch_create(ctypes.byref(b) if out else None, arr, count, None)
+    return st, b
+
+
+@pytest.mark.parametrize("kw", [
+    dict(V=None), dict(W=None), dict(H=None), dict(p=0), dict(n=0), dict(r=0), dict(ldv=7),
+    dict(V=FAKE + 2), dict(W=FAKE + 1), dict(reserved=1), dict(count=0), dict(count=-1),
+    dict(count=16384),
+])
+def test_batch_create_rejects_bad_arguments(kw):
+    st, b = _batch_create(**kw)
+    assert st == nmf.NMF_EINVAL
+    assert b.value is None
+
+
+def test_batch_create_rejects_rank_above_64_and_null_out():
+    st, _ = _batch_create(r=65)
+    assert st == nmf.NMF_EUNSUPPORTED
+    st, _ = _batch_create(out=False)
+    assert st == nmf.NMF_EINVAL
+
+
+def test_batch_null_calls():
+    lib = nmf.load()
+    f = ctypes.c_double()
+    t = (ctypes.c_int32 * nmf.BATCH_TABLE_LEN)()
+    assert lib.nmf_batch_step(None, 1) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_load(None) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_check(None) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_objective(None, ctypes.byref(f)) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_get_table(None, t) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_set_table(None, t) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_tune(None, 1, None) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_solve(None, 1, 1, None, None) == nmf.NMF_EINVAL
+    lib.nmf_batch_destroy(None)  # must not crash
