@@ -170,6 +170,17 @@ nmf_status nmf_profile_stop(nmf_ctx* ctx, double* ms_host, int32_t* launches_hos
 nmf_status nmf_normalize_gauge(float* W, int64_t p, int32_t r, float* H,
                                int64_t n, void* stream);
 
+/* Replace W by the least-squares fit to the current H (a warm start whose H
+   came from elsewhere, e.g. nmf_mlp_predict):
+     W = max(V H^T (H H^T + delta I)^-1, floor),
+   delta = 1e-6 trace(H H^T) / r, floor = floor_rel * max(W) (at least the
+   smallest normal float), so every entry is positive as the multiplicative
+   updates need.  Products as in nmf_step's tier (BF16 tier: bf16 operands),
+   the r x r solve in float64.  Writes the context's W and the caller's W;
+   H is unchanged.  Asynchronous.  Errors: NMF_EINVAL (floor_rel not in
+   (0, 1)), NMF_EUNSUPPORTED (r > 64). */
+nmf_status nmf_refit_w(nmf_ctx* ctx, float floor_rel);
+
 /* ---- Learned warm start -------------------------------------------------
    A small network maps one column v of V (p values) to a starting column of
    H (r values): h0 = softplus(M2 relu(M1 v + b1) + b2), M1 hidden x p,

@@ -246,3 +246,25 @@ def kkt_residual(V, W, H):
     gW, gH = gradients(V, W, H)
     return max(float(np.max(np.abs(np.minimum(_f64(W), gW)))),
                float(np.max(np.abs(np.minimum(_f64(H), gH)))))
+
+
+def ls_dictionary(V, H, floor_rel=1e-3):
+    """Least-squares dictionary for a given H: the warm-start refit of W (an
+    addition to the method: Algorithm 1 only needs some positive start, and
+    the multiplicative updates refine whatever start they get).
+
+        W = max(V H^T (H H^T + delta I)^{-1}, floor)
+        delta = 1e-6 tr(H H^T) / r,  floor = floor_rel * max(0, max W),
+        floor at least the smallest normal float32,
+
+    i.e. the ridge-regularized unconstrained minimizer of ||V - W H||_F^2 over
+    W, clipped to a positive floor so that every entry is a valid start for
+    the multiplicative updates."""
+    V, H = _f64(V), _f64(H)
+    r = H.shape[0]
+    G = H @ H.T
+    tr = float(np.trace(G))
+    delta = 1e-6 * tr / r if tr > 0 else 1e-300
+    W = np.linalg.solve(G + delta * np.eye(r), (V @ H.T).T).T
+    floor = max(floor_rel * max(float(W.max()), 0.0), float(np.finfo(np.float32).tiny))
+    return np.maximum(W, floor)

@@ -152,6 +152,15 @@ hipError_t launch_transpose_f32(const float* src, int64_t lds, int64_t rows,
 // of H (r x n) by that norm; norms: r floats of scratch.
 hipError_t launch_gauge(float* W, int64_t p, int r, float* H, int64_t n, float* norms,
                         hipStream_t st);
+// Least-squares warm-start dictionary (rp <= 64): W = max(A (G + delta I)^-1,
+// floor) from the pass-1 partials A (part, split layout as for the W update)
+// and G = G_H; delta = 1e-6 tr(G)/r, floor = floor_rel * max(W).  Writes Wp
+// (pitch rp) and the caller's W (p x r).  ginv: rp * rp doubles of scratch,
+// maxbits: one word.
+hipError_t launch_ls_refit(const float* G, int rp, int r, int64_t p, const float* part,
+                           int64_t ldp, int64_t sp, int splits, double* ginv,
+                           uint32_t* maxbits, float floor_rel, float* Wp, float* Wcaller,
+                           hipStream_t st);
 // flag |= 1 if some V entry is negative or non-finite.
 hipError_t launch_validate(const float* V, int64_t ldv, int64_t p, int64_t n,
                            uint32_t* flag, hipStream_t st);

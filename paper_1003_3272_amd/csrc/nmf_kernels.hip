@@ -1147,6 +1147,121 @@ __global__ void k_apply_gauge(float* __restrict__ W, int64_t p, int r, float* __
   }
 }
 
+// ---------------------------------------------------------------------------
+// Least-squares dictionary for a warm start (r <= 64):
+//   W = max(A (G + delta I)^{-1}, floor),  A = V H^T,  G = H H^T,
+//   delta = 1e-6 tr(G) / r,  floor = floor_rel * max(W)  (at least FLT_MIN)
+// A comes from the pass-1 partials, G from the Gram reduction of that pass.
+// ---------------------------------------------------------------------------
+// One workgroup: Cholesky factor G + delta I = L L^T in float64, L^{-1} by
+// forward substitution (one column per thread), Ginv = L^{-T} L^{-1}.
+__global__ __launch_bounds__(256) void k_ls_inverse(const float* __restrict__ G, int rp, int r,
+                                                    double* __restrict__ Ginv) {
+  __shared__ double L[64 * 64];
+  __shared__ double Li[64 * 64];
+  __shared__ double s_delta;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < r * r; e += 256) L[e] = (double)G[(e / r) * rp + e % r];
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < r; ++i) t += L[i * r + i];
+    s_delta = t > 0.0 ? 1e-6 * t / r : 1e-300;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += 256) L[i * r + i] += s_delta;
+  __syncthreads();
+  for (int k = 0; k < r; ++k) {
+    if (tid == 0) L[k * r + k] = sqrt(fmax(L[k * r + k], s_delta));
+    __syncthreads();
+    const double dk = L[k * r + k];
+    for (int i = k + 1 + tid; i < r; i += 256) L[i * r + k] /= dk;
+    __syncthreads();
+    const int m = r - k - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) L[i * r + j] -= L[i * r + k] * L[j * r + k];
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < r; j += 256) {
+    for (int i = 0; i < r; ++i) {
+      if (i < j) {
+        Li[i * r + j] = 0.0;
+        continue;
+      }
+      double x = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) x -= L[i * r + k] * Li[k * r + j];
+      Li[i * r + j] = x / L[i * r + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < rp * rp; e += 256) {
+    const int i = e / rp, j = e % rp;
+    double x = 0.0;
+    if (i < r && j < r)
+      for (int k = (i > j ? i : j); k < r; ++k) x += Li[k * r + i] * Li[k * r + j];
+    Ginv[e] = x;
+  }
+}
+
+// 64 rows per workgroup: a_i = sum_s part[s][i] (splits in order), w_i =
+// a_i Ginv with float64 accumulation, written to Wp; the largest entry is
+// folded into maxbits (bits of a nonnegative float order like the values).
+__global__ __launch_bounds__(256) void k_ls_apply(const float* __restrict__ part, int64_t ldp,
+                                                  int64_t sp, int splits,
+                                                  const double* __restrict__ Ginv, int rp, int r,
+                                                  int64_t p, float* __restrict__ Wp,
+                                                  uint32_t* __restrict__ maxbits) {
+  __shared__ float As[64 * 65];
+  __shared__ double Gs[64 * 64];
+  __shared__ float red[256];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  for (int e = tid; e < rp * rp; e += 256) Gs[e] = Ginv[e];
+  for (int e = tid; e < 64 * rp; e += 256) {
+    const int ii = e / rp, k = e % rp;
+    float a = 0.f;
+    if (i0 + ii < p)
+      for (int q = 0; q < splits; ++q) a += part[(int64_t)q * sp + (i0 + ii) * ldp + k];
+    As[ii * 65 + k] = a;
+  }
+  __syncthreads();
+  float mx = 0.f;
+  for (int e = tid; e < 64 * rp; e += 256) {
+    const int ii = e / rp, k = e % rp;
+    if (i0 + ii >= p) continue;
+    double w = 0.0;
+    if (k < r)
+      for (int j = 0; j < r; ++j) w += (double)As[ii * 65 + j] * Gs[j * rp + k];
+    const float wf = (float)w;
+    Wp[(i0 + ii) * rp + k] = wf;
+    mx = fmaxf(mx, wf);
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) atomicMax(maxbits, __float_as_uint(red[0]));
+}
+
+// W <- max(W, floor) on the r live columns; also the caller's W (p x r).
+__global__ void k_ls_clip(float* __restrict__ Wp, int rp, int r, int64_t p,
+                          const uint32_t* __restrict__ maxbits, float floor_rel,
+                          float* __restrict__ Wcaller) {
+  const float fl = fmaxf(floor_rel * __uint_as_float(*maxbits), 1.17549435e-38f);
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < p * r;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / r;
+    const int k = (int)(idx % r);
+    const float w = fmaxf(Wp[i * rp + k], fl);
+    Wp[i * rp + k] = w;
+    Wcaller[idx] = w;
+  }
+}
+
 inline unsigned grid1d(int64_t total, int threads, int64_t cap = 65536) {
   int64_t b = (total + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -1515,6 +1630,19 @@ hipError_t launch_gauge(float* W, int64_t p, int r, float* H, int64_t n, float* 
   hipLaunchKernelGGL(k_col_norms, dim3((unsigned)r), dim3(256), 0, st, W, p, r, norms);
   hipLaunchKernelGGL(k_apply_gauge, dim3(grid1d(p * r + (int64_t)r * n, 256)), dim3(256), 0, st, W,
                      p, r, H, n, norms);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_refit(const float* G, int rp, int r, int64_t p, const float* part, int64_t ldp,
+                           int64_t sp, int splits, double* ginv, uint32_t* maxbits,
+                           float floor_rel, float* Wp, float* Wcaller, hipStream_t st) {
+  if (rp > 64 || r > rp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, maxbits, (int64_t)1, 0u);
+  hipLaunchKernelGGL(k_ls_inverse, dim3(1), dim3(256), 0, st, G, rp, r, ginv);
+  hipLaunchKernelGGL(k_ls_apply, dim3((unsigned)((p + 63) / 64)), dim3(256), 0, st, part, ldp, sp,
+                     splits, ginv, rp, r, p, Wp, maxbits);
+  hipLaunchKernelGGL(k_ls_clip, dim3(grid1d(p * r, 256)), dim3(256), 0, st, Wp, rp, r, p, maxbits,
+                     floor_rel, Wcaller);
   return hipGetLastError();
 }
 

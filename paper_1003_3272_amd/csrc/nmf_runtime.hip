@@ -105,7 +105,8 @@ struct nmf_ctx {
   float* gph = nullptr;  // per-workgroup Grams of H from the H update (fused path)
   double* fpart = nullptr;
   double* fdev = nullptr;
-  uint32_t* flag = nullptr;
+  uint32_t* flag = nullptr;   // [0] validation, [1] refit maximum
+  double* lsinv = nullptr;    // (G_H + delta I)^-1 for nmf_refit_w
   float* VT = nullptr;
   float* WT = nullptr;
   uint16_t* Vb = nullptr;
@@ -376,6 +377,7 @@ nmf_status setup(nmf_ctx* c) {
   const size_t ofp = take(sizeof(double) * (size_t)c->nparts);
   const size_t ofd = take(sizeof(double) * 2);
   const size_t ofl = take(sizeof(uint32_t) * 4);
+  const size_t oli = c->fuse ? take(sizeof(double) * (size_t)rp * rp) : 0;
   size_t oVT = 0, oWT = 0, oVb = 0, oVTb = 0, oHb = 0, oWbT = 0;
   if (!c->bf16) {
     oVT = take(sizeof(float) * (size_t)npad * ppad);
@@ -407,6 +409,7 @@ nmf_status setup(nmf_ctx* c) {
   c->fpart = reinterpret_cast<double*>(base + ofp);
   c->fdev = reinterpret_cast<double*>(base + ofd);
   c->flag = reinterpret_cast<uint32_t*>(base + ofl);
+  if (c->fuse) c->lsinv = reinterpret_cast<double*>(base + oli);
   if (!c->bf16) {
     c->VT = reinterpret_cast<float*>(base + oVT);
     c->WT = reinterpret_cast<float*>(base + oWT);
@@ -606,6 +609,21 @@ nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double*
     if (done) return NMF_OK;
   }
   return NMF_ENOTCONVERGED;
+}
+
+nmf_status nmf_refit_w(nmf_ctx* c, float floor_rel) {
+  if (!c || !(floor_rel > 0.f && floor_rel < 1.f)) return NMF_EINVAL;
+  if (!c->fuse || c->rp > 64) return NMF_EUNSUPPORTED;
+  // A = V H^T as in the W half-step; the same launch reduces G_H
+  const GramRed gr = GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH};
+  const void* X = c->bf16 ? static_cast<const void*>(c->Vb) : static_cast<const void*>(c->Vk);
+  const void* Y = c->bf16 ? static_cast<const void*>(c->Hb) : static_cast<const void*>(c->Hp);
+  TRY_HIP(launch_nt_dma(c->d1, c->bf16, X, c->bf16 ? c->npad : c->ldvk, c->p, Y, c->npad, c->rp,
+                        c->npad, c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, gr,
+                        c->st));
+  TRY_HIP(launch_ls_refit(c->GH, c->rp, c->r, c->p, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits,
+                          c->lsinv, c->flag + 1, floor_rel, c->Wp, c->Wuser, c->st));
+  return NMF_OK;
 }
 
 nmf_status nmf_data_norm2(nmf_ctx* c, double* norm2_host) {

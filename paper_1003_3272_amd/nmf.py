@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.nmf_solve.argtypes = [P, c_int32, POINTER(c_int32), POINTER(c_double),
                               POINTER(c_double), c_int32]
     lib.nmf_solve.restype = c_int32
+    lib.nmf_refit_w.argtypes = [P, ctypes.c_float]
+    lib.nmf_refit_w.restype = c_int32
     lib.nmf_data_norm2.argtypes = [P, POINTER(c_double)]
     lib.nmf_data_norm2.restype = c_int32
     lib.nmf_profile_start.argtypes = [P, c_int32]
@@ -239,6 +241,11 @@ class Nmf:
             ce = self.opts.check_every
             ntr = min(trace_len, 1 + (it.value + ce - 1) // ce)
         return st == NMF_OK, it.value, f.value, [buf[i] for i in range(ntr)]
+
+    def refit_w(self, floor_rel: float = 1e-3):
+        """W <- max(V H^T (H H^T + delta I)^-1, floor_rel * max W): the
+        least-squares dictionary for the current H (asynchronous)."""
+        self._check(load().nmf_refit_w(self._ctx, float(floor_rel)), "nmf_refit_w")
 
     def data_norm2(self) -> float:
         """||V||_F^2 (float64), as used by the gap stopping rule."""

@@ -14,8 +14,10 @@ Pipeline (for a stream of matrices V_m that share a dictionary):
    the result is put in the unit-norm-column gauge, so that its H columns h_j
    are expressed in (nearly) W-bar's basis;
 3. the network is trained on the pairs (v_j, h_j);
-4. a new matrix starts from W0 = W-bar and H0 = network(V) and is refined by
-   the multiplicative updates (which never increase the objective).
+4. a new matrix starts from H0 = network(V) and W0 = W-bar ("net"), or W0 =
+   the least-squares dictionary for H0 clipped to a positive floor
+   (nmf_refit_w, "net_ls"), and is refined by the multiplicative updates
+   (which never increase the objective).
 """
 from __future__ import annotations
 
@@ -108,10 +110,11 @@ def train(net, Vs, Hs, epochs, lr, batch=512, decay=0.9, seed=0, log=None):
 
 
 def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters=20000,
-                 net=None, Wbar=None, seed=None):
+                 net=None, Wbar=None, seed=None, ls_floor=1e-3):
     """Time to reach f / ||V||_F^2 <= tol from a given start (V already on
     the device).  start: "cold" (device U(0,1) draw keyed by `seed`),
-    "wbar" (W-bar and a constant H), or "net" (W-bar and H0 = net(V)).
+    "wbar" (W-bar and a constant H), "net" (W-bar and H0 = net(V)) or
+    "net_ls" (H0 = net(V), W0 refit to H0 by least squares).
     The clock covers everything after V is resident: the start, context
     set-up (casts, copies), every iteration and every objective check.
     Returns a dict with seconds, iterations, final gap and convergence."""
@@ -129,12 +132,16 @@ def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters
                       check_every=check_every, seed=seed)
     else:
         W = Wbar.clone()
-        if start == "net":
+        if start in ("net", "net_ls"):
             H = net.predict(V)
-        else:
+        elif start == "wbar":
             H = torch.full((r, n), 1.0 / r, dtype=torch.float32, device=V.device)
+        else:
+            raise ValueError(f"unknown start {start!r}")
         ctx = nmf.Nmf(V, W, H, precision=precision, tol_kind="gap", tol=tol,
                       check_every=check_every)
+        if start == "net_ls":
+            ctx.refit_w(ls_floor)
     conv, iters, f, _ = ctx.solve(max_iters)
     _sync()
     seconds = time.perf_counter() - t0

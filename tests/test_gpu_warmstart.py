@@ -26,16 +26,52 @@ def test_warm_start_pipeline_small(gpu_lib):
     # goes from about 3e-2 to 2e-3 (a constant predictor scores 8.5e-2)
     print("training loss per epoch:", ["%.3e" % x for x in losses])
     assert losses[-1] < 0.2 * losses[0] and losses[-1] < 1e-2
-    res = {k: [] for k in ("cold", "wbar", "net")}
+    res = {k: [] for k in ("cold", "wbar", "net", "net_ls")}
     for i, V in enumerate(test):
         res["cold"].append(ws.solve_to_gap(V, "cold", tol=2e-3, precision="fp32", seed=9000 + i,
                                            Wbar=Wbar))
         res["wbar"].append(ws.solve_to_gap(V, "wbar", tol=2e-3, precision="bf16", Wbar=Wbar))
         res["net"].append(ws.solve_to_gap(V, "net", tol=2e-3, precision="bf16", Wbar=Wbar,
                                           net=net))
+        res["net_ls"].append(ws.solve_to_gap(V, "net_ls", tol=2e-3, precision="bf16",
+                                             Wbar=Wbar, net=net))
     for k, v in res.items():
         assert all(x["converged"] and x["gap"] <= 2e-3 for x in v), (k, v)
     it = {k: np.median([x["iters"] for x in v]) for k, v in res.items()}
     print("median iterations to gap 2e-3:", it)
     assert it["net"] < it["cold"]
     net.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_refit_w_matches_oracle(gpu_lib, precision):
+    """nmf_refit_w against the oracle's least-squares dictionary on the same
+    inputs (bf16-rounded V and H for the BF16 tier).  Products accumulate in
+    float32 and the r x r solve runs in float64, so the error is bounded by
+    about cond(H H^T) times the float32 product error; the bar is
+    max(1e-4, 2e-6 cond)."""
+    from oracle import nmf_oracle as o
+    from paper_1003_3272_amd import nmf
+    p, n, r = 300, 700, 20
+    Wb = g.warm_start_base(p=p, r=r, seed=78)
+    V, _, Hs = g.warm_start_matrix(Wb, 3, n=n)
+    rng = np.random.default_rng(5)
+    H = (Hs * rng.lognormal(0.0, 0.2, size=Hs.shape) + 1e-3).astype(np.float32)
+    W0 = np.full((p, r), 0.5, np.float32)
+    Vd, Wd, Hd = (torch.from_numpy(x).cuda() for x in (V, W0, H))
+    with nmf.Nmf(Vd, Wd, Hd, precision=precision) as c:
+        c.refit_w(1e-3)
+        f = c.objective()
+        Wg = Wd.cpu().numpy()
+    assert torch.equal(Hd.cpu(), torch.from_numpy(H))
+    Vr, Hr = (o.bf16_round(V), o.bf16_round(H)) if precision == "bf16" else (V, H)
+    Wo = o.ls_dictionary(Vr, Hr, 1e-3)
+    Hr64 = np.asarray(Hr, np.float64)
+    kappa = np.linalg.cond(Hr64 @ Hr64.T)
+    err = np.linalg.norm(Wg - Wo) / np.linalg.norm(Wo)
+    print(f"{precision}: refit error {err:.2e}, cond {kappa:.1e}")
+    assert err < max(1e-4, 2e-6 * kappa)
+    assert Wg.min() > 0
+    # the context carries the refit W: its objective is f(V, W_refit, H)
+    fo = o.objective(V, Wg, H)
+    assert abs(f - fo) <= 1e-6 * fo

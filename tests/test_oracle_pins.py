@@ -299,3 +299,49 @@ def test_rel_change_stop_agrees_with_plain_run():
     first = int(np.argmax(stat < tol)) + 1
     _, _, k, f, _ = o.solve(V, W0, H0, 200, tol=tol)
     assert k == first and f == tr[first]
+
+
+# ---- least-squares warm-start dictionary ------------------------------------
+
+def test_ls_dictionary_recovers_exact_factor():
+    """V = W* H with W* > 0 and H of full row rank: the least-squares W is W*
+    (up to the 1e-6 relative ridge), and nothing is clipped."""
+    rng = np.random.default_rng(31)
+    Ws = rng.uniform(0.5, 1.5, size=(40, 6))
+    H = rng.uniform(0.0, 1.0, size=(6, 90))
+    W = o.ls_dictionary(Ws @ H, H)
+    assert np.linalg.norm(W - Ws) / np.linalg.norm(Ws) < 1e-4
+
+
+def test_ls_dictionary_normal_equations():
+    """Interior solution: the residual satisfies the ridge normal equations
+    (V - W H) H^T = delta W with delta = 1e-6 tr(H H^T) / r."""
+    rng = np.random.default_rng(32)
+    H = rng.uniform(0.0, 1.0, size=(5, 70))
+    V = rng.uniform(0.5, 1.0, size=(30, 5)) @ H + 0.01 * rng.uniform(size=(30, 70))
+    W = o.ls_dictionary(V, H)
+    delta = 1e-6 * np.trace(H @ H.T) / 5
+    lhs = (V - W @ H) @ H.T
+    assert np.allclose(lhs, delta * W, atol=1e-9 * np.abs(V @ H.T).max())
+
+
+def test_ls_dictionary_scaling_and_floor():
+    """Rescaling the rows of H by D rescales the columns of W by D^-1 (the
+    ridge scales with tr, so only to its order); an unconstrained solution
+    with negative entries is clipped to floor_rel * max(W) and stays positive."""
+    rng = np.random.default_rng(33)
+    H = rng.uniform(0.0, 1.0, size=(4, 60))
+    Ws = rng.uniform(0.5, 1.5, size=(25, 4))
+    V = Ws @ H
+    D = np.array([2.0, 0.5, 4.0, 1.0])
+    W1 = o.ls_dictionary(V, H)
+    W2 = o.ls_dictionary(V, D[:, None] * H)
+    assert np.allclose(W2 * D, W1, rtol=1e-4)
+    # a data column pattern that needs a negative coefficient: V = W* H with
+    # one column of W* negative
+    Wn = Ws.copy()
+    Wn[:, 2] = -0.3
+    W3 = o.ls_dictionary(Wn @ H, H, floor_rel=1e-2)
+    assert W3.min() > 0
+    assert np.allclose(W3[:, 2], 1e-2 * W3.max())
+    assert np.allclose(W3[:, [0, 1, 3]], Wn[:, [0, 1, 3]], rtol=1e-4)
