@@ -254,10 +254,11 @@ typedef struct {
 #define NMF_BATCH_TABLE_LEN 9
 
 /* Copy the problem list (host array of `count` <= 16383 entries), allocate
-   the workspace (padded working factors, Grams, partials) and load W, H.
-   V, W and H stay owned by the caller and must outlive the batch.  V needs
-   only 4-byte alignment (an aligned copy is kept where it lacks 16 bytes
-   or ldv % 4 != 0).  Errors: NMF_EINVAL (null pointer, p, n or r < 1,
+   the workspace and load V, W and H.  V is copied once, here, into padded
+   row-major and transposed copies (about 2 x 4 bytes per entry of V) that
+   the steps read; a later change to the caller's V is not seen.  W and H
+   stay owned by the caller and must outlive the batch.  Pointers need
+   4-byte alignment only.  Errors: NMF_EINVAL (null pointer, p, n or r < 1,
    ldv < n, reserved != 0), NMF_EUNSUPPORTED (r > 64), NMF_ENOMEM. */
 nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs,
                             int32_t count, void* stream);

@@ -46,14 +46,17 @@ __device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
 }
 
 constexpr int kThreads = 256;
-constexpr int BK = 32;        // reduction slots per LDS stage
-constexpr int PW = BK + 4;    // pitch of k-contiguous LDS rows (phase W)
+constexpr int S = 3;          // copy-ring stages in flight
 constexpr int kMaxNB = 128;
 constexpr int kMaxMB = 128;
-constexpr int kLdsFloats = 2 * BK * (kMaxNB + 16) + 2 * BK * 80;  // 14336 floats
-static_assert(2 * kMaxMB * PW + 2 * 64 * PW <= kLdsFloats, "phase W stage fits");
-static_assert(64 * (kMaxNB + 16) + 64 * 80 <= kLdsFloats, "phase H epilogue fits");
-static_assert(kMaxMB * 68 + 64 * 68 <= kLdsFloats, "phase W epilogue fits");
+constexpr int kLdsBytes = S * (kMaxMB + 64) * 128;  // 72 KB: two workgroups per CU
+static_assert((kMaxMB * 68 + 64 * 68) * 4 <= kLdsBytes, "phase W epilogue fits");
+static_assert((64 * (kMaxNB + 16) + 64 * 80) * 4 <= kLdsBytes, "phase H epilogue fits");
+
+// The persistent kernel's LDS: the copy ring during a tile's product, then
+// the tile's epilogue.  At namespace scope so that the out-of-line tile
+// functions address it directly (as LDS, not through generic pointers).
+__shared__ __attribute__((aligned(1024))) char g_lds[kLdsBytes];
 
 // A wait longer than this many ticks of the 100 MHz constant clock (2 s)
 // means the schedule is broken: raise the error flag and leave.
@@ -63,18 +66,22 @@ constexpr uint64_t kWaitTicks = 200000000ull;
 
 // Per-problem descriptor (device copy; see the host builder for meaning).
 struct Prob {
-  const float* V;
+  float* V;      // padded copy of V: rows round_up(p, 128), pitch ldv = round_up(n, 32)
+  float* VT;     // padded V^T: rows round_up(n, 128), pitch ldvt = round_up(p, 32)
+  const float* Vsrc;  // caller's V (read once, at creation)
   float* Wp;     // p x rp, pitch rp (working W, padded columns zero)
-  float* Hp;     // rp x ldh (working H, padded rows and columns zero)
+  float* WT;     // W^T: rpy x ldwt (ldwt = round_up(p, 32)), padding zero
+  float* Hp;     // rpy x ldh (ldh = round_up(n, 32)), padded rows and columns zero
   float* GH;     // rp x rp
   float* GW;     // rp x rp
   float* gpart;  // max(tilesW, tilesH) x rp x rp partial Grams
   float* W;      // caller's W (p x r)
   float* H;      // caller's H (r x n)
-  int64_t ldv, ldh;
-  int32_t p, n, r, rp;
-  int32_t msw, msh;  // phase W tile rows = 64 msw; phase H tile columns = 64 msh
+  int64_t ldv, ldvt, ldsrc, ldh, ldwt;
+  int32_t p, n, r, rp;  // rp = r rounded up to 16; rpy = rp rounded up to 32
+  int32_t msw, msh;     // phase W tile rows = 64 msw; phase H tile columns = 64 msh
   int32_t tilesW, tilesH;
+  int32_t kw, kh;       // 32-float stages along n (phase W) and along p (phase H)
 };
 
 // Counter block, cleared before every launch: [0] queue head, [32] error
@@ -180,88 +187,121 @@ __device__ __forceinline__ float4 lds4(const float* p) {
 }
 
 // ---------------------------------------------------------------------------
-// Phase W tile: MB = 64 MS rows, rank padded to RP = 16 NT.  Wave w owns
-// rows [16 MS w, 16 MS (w+1)); each lane reads 4 consecutive k of a row with
-// one 128-bit LDS load and feeds four MFMAs (slot g of MFMA e is k = 4g + e
-// within the 16-k group), for A and B alike.
+// The product of a tile, C[m][c] = sum_k X[m][k] Y[c][k] (m < MB = 64 MS,
+// c < RPY = 32 or 64 rows of Y), both operands contiguous along k and zero
+// beyond the data, through an asynchronous global -> LDS copy ring: a stage
+// is MB + RPY rows of 128 bytes (32 floats of k) copied by
+// global_load_lds_dwordx4 (no register staging) with 3 stages in flight.
+// Inside a row, 16-byte chunk q sits at slot q ^ (row % 8), so the 16 rows
+// of an MFMA fragment read distinct banks.  Wave w owns rows
+// [16 MS w, 16 MS (w+1)); a lane's 128-bit read holds 4 consecutive k that
+// feed four MFMAs (slot g of MFMA e is k = 4g + e within the 16-k group),
+// for A and B alike.
 // ---------------------------------------------------------------------------
-template <int MS, int NT>
-__device__ void tile_w(const Prob& P, int t, float* lds) {
-  constexpr int MB = 64 * MS, RP = 16 * NT;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, c = lane & 15, g = lane >> 4;
-  const int64_t p0 = (int64_t)t * MB;
-  const int64_t n = P.n, p = P.p;
-  float* Vs = lds;                     // [2][MB][PW]
-  float* Hs = lds + 2 * kMaxMB * PW;   // [2][RP][PW]
-  constexpr int NV = MB * (BK / 4) / kThreads;                  // float4 per thread (V)
-  constexpr int NH = (RP * (BK / 4) + kThreads - 1) / kThreads;  // float4 per thread (H)
-  float4 rv[NV], rh[NH];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
-      rv[u] = ld4(P.V, P.ldv, p0 + row, p, k0 + 4 * q, n);
-    }
-#pragma unroll
-    for (int u = 0; u < NH; ++u) {
-      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
-      rh[u] = (idx < RP * (BK / 4)) ? ld4(P.Hp, P.ldh, row, RP, k0 + 4 * q, n)
-                                    : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
-      st4(&Vs[(buf * kMaxMB + row) * PW + 4 * q], rv[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < NH; ++u) {
-      const int idx = tid + kThreads * u, row = idx >> 3, q = idx & 7;
-      if (idx < RP * (BK / 4)) st4(&Hs[(buf * 64 + row) * PW + 4 * q], rh[u]);
-    }
-  };
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-  v4f acc[MS][NT];
+// s_waitcnt vmcnt(VM) (gfx9 encoding, vmcnt split over bits 3:0 and
+// 15:14), leaving expcnt and lgkmcnt unconstrained.
+template <int VM>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(VM >= 0 && VM < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((VM & 0xF) | (0x7 << 4) | (0xF << 8) | (((VM >> 4) & 0x3) << 14));
+}
+
+// Barrier for the ring: a __syncthreads() would also wait for every
+// outstanding copy (they are counted by vmcnt); this one retires the wave's
+// own LDS reads and meets at a bare s_barrier.  The asm statements keep the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void ring_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int MS, int NT>
+__device__ __forceinline__ void ring_nt(const float* __restrict__ X, int64_t ldx,
+                                        const float* __restrict__ Y, int64_t ldy, int nst,
+                                        char* lds, v4f (&acc)[MS][NT]) {
+  constexpr int MB = 64 * MS, RPY = (NT <= 2) ? 32 : 64, ROWS = MB + RPY;
+  constexpr int L = ROWS / 32;  // copy instructions per wave per stage
+  constexpr int STAGE = ROWS * 128;
+  static_assert(ROWS % 32 == 0 && S * STAGE <= kLdsBytes, "stage layout");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c = lane & 15, g = lane >> 4;
+  // lane's source in copy j: stage row rr = 8 (wave L + j) + lane / 8, slot
+  // lane % 8, holding chunk (lane % 8) ^ (rr % 8) = (lane % 8) ^ (lane / 8)
+  const int chunk = (lane & 7) ^ (lane >> 3);
+  const char* src[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const int rr = 8 * (wave * L + j) + (lane >> 3);
+    src[j] = rr < MB ? reinterpret_cast<const char*>(X + rr * ldx) + 16 * chunk
+                     : reinterpret_cast<const char*>(Y + (rr - MB) * ldy) + 16 * chunk;
+  }
+  auto issue = [&](int st) {
+    char* dst = lds + (st % S) * STAGE;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(src[j] + (int64_t)st * 128),
+                                       (lds_ptr_t)(dst + (wave * L + j) * 1024), 16, 0, 0);
+  };
 #pragma unroll
   for (int a = 0; a < MS; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-
-  const int wrow = 16 * MS * wv;
-  const int nch = (int)((n + BK - 1) / BK);
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) gload((int64_t)(ch + 1) * BK);
-    const float* vb = Vs + buf * kMaxMB * PW;
-    const float* hb = Hs + buf * 64 * PW;
+  const int wrow = 16 * MS * wave;
+  auto compute = [&](const char* buf) {
 #pragma unroll
-    for (int s = 0; s < BK / 16; ++s) {
-      float4 a[MS], b[NT];
-#pragma unroll
-      for (int ms = 0; ms < MS; ++ms) a[ms] = lds4(&vb[(wrow + 16 * ms + c) * PW + 16 * s + 4 * g]);
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[nt] = lds4(&hb[(16 * nt + c) * PW + 16 * s + 4 * g]);
+    for (int kk = 0; kk < 2; ++kk) {
+      const int off = 16 * ((4 * kk + g) ^ (c & 7));
+      v4f a[MS], b[NT];
 #pragma unroll
       for (int ms = 0; ms < MS; ++ms)
+        a[ms] = *reinterpret_cast<const v4f*>(buf + (wrow + 16 * ms + c) * 128 + off);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          acc[ms][nt] = mfma(a[ms].x, b[nt].x, acc[ms][nt]);
-          acc[ms][nt] = mfma(a[ms].y, b[nt].y, acc[ms][nt]);
-          acc[ms][nt] = mfma(a[ms].z, b[nt].z, acc[ms][nt]);
-          acc[ms][nt] = mfma(a[ms].w, b[nt].w, acc[ms][nt]);
-        }
+      for (int nt = 0; nt < NT; ++nt)
+        b[nt] = *reinterpret_cast<const v4f*>(buf + (MB + 16 * nt + c) * 128 + off);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int ms = 0; ms < MS; ++ms)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[ms][nt] = mfma(a[ms][e], b[nt][e], acc[ms][nt]);
     }
-    if (ch + 1 < nch) sstore(buf ^ 1);
-    __syncthreads();
+  };
+  // Stage st lives in buffer st % S.  At the top of iteration st, stages st
+  // and (if it exists) st + 1 have been issued; once this wave's copies of
+  // stage st have landed, one barrier certifies that every wave's copies of
+  // stage st are in LDS and that every wave has finished computing stage
+  // st - 1, whose buffer is then refilled with stage st + 2.
+  const int pre = nst < S - 1 ? nst : S - 1;
+  for (int st = 0; st < pre; ++st) issue(st);
+  for (int st = 0; st < nst; ++st) {
+    if (st + 1 < nst) wait_vm<L>();
+    else wait_vm<0>();
+    ring_barrier();
+    if (st + S - 1 < nst) issue(st + S - 1);
+    compute(lds + (st % S) * STAGE);
   }
+  __syncthreads();  // every wave is done with the ring before the epilogue reuses it
+}
 
-  // ---- epilogue: B = W_rows G_H, W <- W * (A / B), partial Gram ----------
+// ---------------------------------------------------------------------------
+// Phase W tile t: rows [t MB, t MB + MB) of V, K = n.
+// ---------------------------------------------------------------------------
+template <int MS, int NT>
+__device__ __attribute__((noinline)) void tile_w(const Prob& P, int t) {
+  constexpr int MB = 64 * MS, RP = 16 * NT;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, c = lane & 15, g = lane >> 4;
+  const int64_t p0 = (int64_t)t * MB;
+  const int64_t p = P.p;
+  v4f acc[MS][NT];
+  ring_nt<MS, NT>(P.V + p0 * P.ldv, P.ldv, P.Hp, P.ldh, P.kw, g_lds, acc);
+  float* lds = reinterpret_cast<float*>(g_lds);
+  const int wrow = 16 * MS * wv;
+
+  // ---- epilogue: B = W_rows G_H, W <- W * (A / B), W^T, partial Gram -----
   constexpr int PS = RP + 4;
-  float* Ws = lds;               // [MB][PS]
+  float* Ws = lds;                // [MB][PS]
   float* Gs = lds + kMaxMB * 68;  // [RP][PS]
   for (int idx = tid; idx < MB * (RP / 4); idx += kThreads) {
     const int row = idx / (RP / 4), q = idx % (RP / 4);
@@ -296,7 +336,7 @@ __device__ void tile_w(const Prob& P, int t, float* lds) {
         den[ms][nt] = mfma(a[ms].w, b[nt].w, den[ms][nt]);
       }
   }
-  float wn[MS][NT][4];
+  // new W in place of the numerators
 #pragma unroll
   for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
@@ -305,7 +345,7 @@ __device__ void tile_w(const Prob& P, int t, float* lds) {
       for (int v = 0; v < 4; ++v) {
         const int lr = wrow + 16 * ms + 4 * g + v, col = 16 * nt + c;
         const float w = Ws[lr * PS + col], d = den[ms][nt][v];
-        wn[ms][nt][v] = (d > 0.f) ? w * (acc[ms][nt][v] / d) : w;
+        acc[ms][nt][v] = (d > 0.f) ? w * (acc[ms][nt][v] / d) : w;
       }
   // the wave's own rows only (its reads above are done)
 #pragma unroll
@@ -313,11 +353,23 @@ __device__ void tile_w(const Prob& P, int t, float* lds) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Ws[(wrow + 16 * ms + 4 * g + v) * PS + 16 * nt + c] = wn[ms][nt][v];
+      for (int v = 0; v < 4; ++v) Ws[(wrow + 16 * ms + 4 * g + v) * PS + 16 * nt + c] = acc[ms][nt][v];
   __syncthreads();
   for (int idx = tid; idx < MB * (RP / 4); idx += kThreads) {
     const int row = idx / (RP / 4), q = idx % (RP / 4);
     if (p0 + row < p) st4(&P.Wp[(p0 + row) * RP + 4 * q], lds4(&Ws[row * PS + 4 * q]));
+  }
+  // W^T (RP x ldwt), the operand of the phase-H products: 4 rows of W per store
+  for (int idx = tid; idx < RP * (MB / 4); idx += kThreads) {
+    const int k = idx / (MB / 4), r0 = 4 * (idx % (MB / 4));
+    float* dst = P.WT + (int64_t)k * P.ldwt + p0 + r0;
+    if (p0 + r0 + 3 < p) {
+      st4(dst, make_float4(Ws[r0 * PS + k], Ws[(r0 + 1) * PS + k], Ws[(r0 + 2) * PS + k],
+                           Ws[(r0 + 3) * PS + k]));
+    } else {
+      for (int e = 0; e < 4; ++e)
+        if (p0 + r0 + e < p) dst[e] = Ws[(r0 + e) * PS + k];
+    }
   }
   // partial Gram C[i][j] = sum_m Wn[m][i] Wn[m][j] over the tile's rows
   float* gp = P.gpart + (int64_t)t * RP * RP;
@@ -333,84 +385,23 @@ __device__ void tile_w(const Prob& P, int t, float* lds) {
 }
 
 // ---------------------------------------------------------------------------
-// Phase H tile: NB = 64 MS columns of V, rank RP = 16 NT.  The reduction
-// runs down the rows of V (k = row index), so operands are read from LDS one
-// float per lane (row k = 4 s + g, 16 consecutive columns per lane group);
-// pitches are chosen so the four groups fall in distinct banks.
+// Phase H tile t: columns [t NB, t NB + NB) of V (rows of V^T), K = p.
 // ---------------------------------------------------------------------------
 template <int MS, int NT>
-__device__ void tile_h(const Prob& P, int t, float* lds) {
+__device__ __attribute__((noinline)) void tile_h(const Prob& P, int t) {
   constexpr int NB = 64 * MS, RP = 16 * NT;
   constexpr int PV = NB + 16;
   constexpr int PR = (RP == 48) ? 80 : RP + 16;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, c = lane & 15, g = lane >> 4;
   const int64_t j0 = (int64_t)t * NB;
-  const int64_t n = P.n, p = P.p;
-  float* Vs = lds;                          // [2][BK][PV]
-  float* Ws = lds + 2 * BK * (kMaxNB + 16);  // [2][BK][PR]
-  constexpr int NV = BK * (NB / 4) / kThreads;
-  constexpr int NW = (BK * (RP / 4) + kThreads - 1) / kThreads;
-  float4 rv[NV], rw[NW];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      const int idx = tid + kThreads * u, row = idx / (NB / 4), q = idx % (NB / 4);
-      rv[u] = ld4(P.V, P.ldv, k0 + row, p, j0 + 4 * q, n);
-    }
-#pragma unroll
-    for (int u = 0; u < NW; ++u) {
-      const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
-      rw[u] = (idx < BK * (RP / 4)) ? ld4(P.Wp, RP, k0 + row, p, 4 * q, RP)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      const int idx = tid + kThreads * u, row = idx / (NB / 4), q = idx % (NB / 4);
-      st4(&Vs[(buf * BK + row) * PV + 4 * q], rv[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < NW; ++u) {
-      const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
-      if (idx < BK * (RP / 4)) st4(&Ws[(buf * BK + row) * PR + 4 * q], rw[u]);
-    }
-  };
-
+  const int64_t n = P.n;
   v4f acc[MS][NT];
-#pragma unroll
-  for (int a = 0; a < MS; ++a)
-#pragma unroll
-    for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-
+  ring_nt<MS, NT>(P.VT + j0 * P.ldvt, P.ldvt, P.WT, P.ldwt, P.kh, g_lds, acc);
+  float* lds = reinterpret_cast<float*>(g_lds);
   const int wcol = 16 * MS * wv;
-  const int nch = (int)((p + BK - 1) / BK);
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) gload((int64_t)(ch + 1) * BK);
-    const float* vb = Vs + buf * BK * PV;
-    const float* wb = Ws + buf * BK * PR;
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      float a[MS], b[NT];
-#pragma unroll
-      for (int ms = 0; ms < MS; ++ms) a[ms] = vb[(kk + g) * PV + wcol + 16 * ms + c];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[nt] = wb[(kk + g) * PR + 16 * nt + c];
-#pragma unroll
-      for (int ms = 0; ms < MS; ++ms)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[ms][nt] = mfma(a[ms], b[nt], acc[ms][nt]);
-    }
-    if (ch + 1 < nch) sstore(buf ^ 1);
-    __syncthreads();
-  }
 
   // ---- epilogue: D^T = H_cols^T G_W, H <- H * (S / D), partial Gram ------
-  float* Hs = lds;                     // [RP][PV]
+  float* Hs = lds;                       // [RP][PV]
   float* Gs = lds + 64 * (kMaxNB + 16);  // [RP][PR]
   for (int idx = tid; idx < RP * (NB / 4); idx += kThreads) {
     const int row = idx / (NB / 4), q = idx % (NB / 4);
@@ -438,7 +429,7 @@ __device__ void tile_h(const Prob& P, int t, float* lds) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) den[ms][nt] = mfma(a[ms], b[nt], den[ms][nt]);
   }
-  float hn[MS][NT][4];
+  // new H in place of the numerators
 #pragma unroll
   for (int ms = 0; ms < MS; ++ms)
 #pragma unroll
@@ -447,7 +438,7 @@ __device__ void tile_h(const Prob& P, int t, float* lds) {
       for (int v = 0; v < 4; ++v) {
         const int m = wcol + 16 * ms + 4 * g + v, k = 16 * nt + c;
         const float h = Hs[k * PV + m], d = den[ms][nt][v];
-        hn[ms][nt][v] = (d > 0.f) ? h * (acc[ms][nt][v] / d) : h;
+        acc[ms][nt][v] = (d > 0.f) ? h * (acc[ms][nt][v] / d) : h;
       }
   // the wave's own columns only (its reads above are done)
 #pragma unroll
@@ -455,10 +446,10 @@ __device__ void tile_h(const Prob& P, int t, float* lds) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Hs[(16 * nt + c) * PV + wcol + 16 * ms + 4 * g + v] = hn[ms][nt][v];
+      for (int v = 0; v < 4; ++v) Hs[(16 * nt + c) * PV + wcol + 16 * ms + 4 * g + v] = acc[ms][nt][v];
   __syncthreads();
-  // columns >= n hold zeros (masked loads, zero numerators), and the rows
-  // of Hp are padded to a multiple of 4 columns, so whole float4s are stored
+  // columns >= n hold zeros (masked loads, zero numerators) and rows of Hp
+  // are padded to a multiple of 32 columns, so whole float4s are stored
   for (int idx = tid; idx < RP * (NB / 4); idx += kThreads) {
     const int row = idx / (NB / 4), q = idx % (NB / 4);
     if (j0 + 4 * q < n) st4(&P.Hp[row * P.ldh + j0 + 4 * q], lds4(&Hs[row * PV + 4 * q]));
@@ -492,7 +483,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __
                                                                uint32_t per_iter, uint32_t total,
                                                                uint32_t* __restrict__ ctr,
                                                                uint32_t* __restrict__ sticky) {
-  __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
   __shared__ uint32_t s_slot;
   __shared__ int s_flag;
   for (;;) {
@@ -512,7 +502,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __
       switch (P.msw * 8 + P.rp / 16) {
 #define CASE_W(MS, NT) \
   case MS * 8 + NT:    \
-    tile_w<MS, NT>(P, t, lds); \
+    tile_w<MS, NT>(P, t); \
     break;
         NMFB_CASES(CASE_W)
 #undef CASE_W
@@ -524,7 +514,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __
       switch (P.msh * 8 + P.rp / 16) {
 #define CASE_H(MS, NT) \
   case MS * 8 + NT:    \
-    tile_h<MS, NT>(P, t, lds); \
+    tile_h<MS, NT>(P, t); \
     break;
         NMFB_CASES(CASE_H)
 #undef CASE_H
@@ -537,6 +527,33 @@ __global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __
 }
 
 // Set-up and copy kernels (grid.y = problem).
+// The caller's V into the padded copies V (row-major) and V^T through
+// 32 x 32 LDS tiles, so both copies are written with coalesced stores.
+__global__ __launch_bounds__(256) void k_batch_pad(const Prob* __restrict__ probs) {
+  __shared__ float sh[32][33];
+  const Prob& P = probs[blockIdx.y];
+  const int ti = (P.p + 31) / 32, tj = (P.n + 31) / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int tile = blockIdx.x; tile < ti * tj; tile += gridDim.x) {
+    const int64_t i0 = (int64_t)(tile / tj) * 32, j0 = (int64_t)(tile % tj) * 32;
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      const int64_t i = i0 + k, j = j0 + tx;
+      float v = 0.f;
+      if (i < P.p && j < P.n) {
+        v = P.Vsrc[i * P.ldsrc + j];
+        P.V[i * P.ldv + j] = v;
+      }
+      sh[k][tx] = v;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      const int64_t j = j0 + k, i = i0 + tx;
+      if (i < P.p && j < P.n) P.VT[j * P.ldvt + i] = sh[tx][k];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_batch_load(const Prob* __restrict__ probs) {
   const Prob P = probs[blockIdx.y];
   const int64_t nw = (int64_t)P.p * P.rp, nh = (int64_t)P.rp * P.ldh;
@@ -683,7 +700,6 @@ struct nmf_batch {
   int device = 0, cus = 0;
   std::vector<nmf_problem> user;
   std::vector<Prob> host;       // descriptors (device pointers)
-  std::vector<float*> vcopy;    // aligned copies of V where the caller's is not
   char* arena = nullptr;        // factors, Grams, partials (one allocation)
   size_t factor_bytes = 0;      // leading part of the arena that tuning saves
   Prob* dprobs = nullptr;
@@ -854,16 +870,19 @@ nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t c
       hipSuccess)
     return fail(NMF_EDEVICE);
   // arena: Wp and Hp of all problems, then G_H of all problems (together
-  // the state that tuning saves and restores), then G_W and partials
+  // the state that tuning saves and restores), then G_W, partial Grams, W^T,
+  // and the padded copies of V and V^T
   size_t off = 0;
-  std::vector<size_t> oW(count), oH(count), oGH(count), oGW(count), oP(count);
+  std::vector<size_t> oW(count), oH(count), oGH(count), oGW(count), oP(count), oWT(count),
+      oV(count), oVT(count);
+  auto rpy_of = [](int64_t rp) { return up(rp, 32); };
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = probs[i];
-    const int rp = (int)up(q.r, 16);
+    const int64_t rp = up(q.r, 16);
     oW[i] = off;
     off += up(q.p * rp * 4, 256);
     oH[i] = off;
-    off += up((int64_t)rp * up(q.n, 4) * 4, 256);
+    off += up(rpy_of(rp) * up(q.n, 32) * 4, 256);
   }
   for (int i = 0; i < count; ++i) {
     const int64_t rp = up(probs[i].r, 16);
@@ -880,32 +899,38 @@ nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t c
     const int64_t tiles = std::max((q.p + 63) / 64, (q.n + 63) / 64);
     oP[i] = off;
     off += up(tiles * rp * rp * 4, 256);
+    oWT[i] = off;
+    off += up(rpy_of(rp) * up(q.p, 32) * 4, 256);
+  }
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = probs[i];
+    oV[i] = off;
+    off += up(up(q.p, 128) * up(q.n, 32) * 4, 1024);
+    oVT[i] = off;
+    off += up(up(q.n, 128) * up(q.p, 32) * 4, 1024);
   }
   if (hipMalloc(&b->arena, off) != hipSuccess) return fail(NMF_ENOMEM);
   if (hipMemsetAsync(b->arena, 0, off, b->st) != hipSuccess) return fail(NMF_EDEVICE);
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = probs[i];
     Prob& P = b->host[i];
-    P.V = q.V;
-    P.ldv = q.ldv;
-    if (reinterpret_cast<uintptr_t>(q.V) % 16 || q.ldv % 4) {
-      // the tile loaders read 16-byte vectors: keep an aligned copy
-      float* cp = nullptr;
-      const int64_t ld = up(q.n, 4);
-      if (hipMalloc(&cp, q.p * ld * 4) != hipSuccess) return fail(NMF_ENOMEM);
-      b->vcopy.push_back(cp);
-      if (nmfk::launch_copy_pad(q.V, q.ldv, q.p, q.n, cp, ld, b->st) != hipSuccess)
-        return fail(NMF_EDEVICE);
-      P.V = cp;
-      P.ldv = ld;
-    }
+    P.Vsrc = q.V;
+    P.ldsrc = q.ldv;
+    P.V = reinterpret_cast<float*>(b->arena + oV[i]);
+    P.ldv = up(q.n, 32);
+    P.VT = reinterpret_cast<float*>(b->arena + oVT[i]);
+    P.ldvt = up(q.p, 32);
     P.p = (int32_t)q.p;
     P.n = (int32_t)q.n;
     P.r = q.r;
     P.rp = (int32_t)up(q.r, 16);
-    P.ldh = up(q.n, 4);
+    P.ldh = up(q.n, 32);
+    P.ldwt = up(q.p, 32);
+    P.kw = (int32_t)(P.ldv / 32);
+    P.kh = (int32_t)(P.ldvt / 32);
     P.Wp = reinterpret_cast<float*>(b->arena + oW[i]);
     P.Hp = reinterpret_cast<float*>(b->arena + oH[i]);
+    P.WT = reinterpret_cast<float*>(b->arena + oWT[i]);
     P.GH = reinterpret_cast<float*>(b->arena + oGH[i]);
     P.GW = reinterpret_cast<float*>(b->arena + oGW[i]);
     P.gpart = reinterpret_cast<float*>(b->arena + oP[i]);
@@ -942,6 +967,8 @@ nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t c
     return fail(NMF_EDEVICE);
   s = plan(b);
   if (s != NMF_OK) return fail(s);
+  hipLaunchKernelGGL(k_batch_pad, dim3(256, (unsigned)count), dim3(256), 0, b->st, b->dprobs);
+  if (hipGetLastError() != hipSuccess) return fail(NMF_EDEVICE);
   s = nmf_batch_load(b);
   if (s != NMF_OK) return fail(s);
   if (hipStreamSynchronize(b->st) != hipSuccess) return fail(NMF_EDEVICE);
@@ -1088,7 +1115,6 @@ void nmf_batch_destroy(nmf_batch* b) {
   (void)hipStreamSynchronize(b->st);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  for (float* p : b->vcopy) (void)hipFree(p);
   if (b->arena) (void)hipFree(b->arena);
   if (b->dprobs) (void)hipFree(b->dprobs);
   if (b->ctr) (void)hipFree(b->ctr);

@@ -110,11 +110,13 @@ def train(net, Vs, Hs, epochs, lr, batch=512, decay=0.9, seed=0, log=None):
 
 
 def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters=20000,
-                 net=None, Wbar=None, seed=None, ls_floor=1e-3):
+                 net=None, Wbar=None, seed=None, ls_floor=1e-3, hfit=20):
     """Time to reach f / ||V||_F^2 <= tol from a given start (V already on
     the device).  start: "cold" (device U(0,1) draw keyed by `seed`),
-    "wbar" (W-bar and a constant H), "net" (W-bar and H0 = net(V)) or
-    "net_ls" (H0 = net(V), W0 refit to H0 by least squares).
+    "wbar" (W-bar and a constant H), "net" (W-bar and H0 = net(V)),
+    "net_ls" (H0 = net(V), W0 refit to H0 by least squares) or "hfit_ls"
+    (no network: H fitted to W-bar by `hfit` H-only multiplicative updates
+    from a constant H, then W0 refit to that H).
     The clock covers everything after V is resident: the start, context
     set-up (casts, copies), every iteration and every objective check.
     Returns a dict with seconds, iterations, final gap and convergence."""
@@ -134,13 +136,16 @@ def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters
         W = Wbar.clone()
         if start in ("net", "net_ls"):
             H = net.predict(V)
-        elif start == "wbar":
+        elif start in ("wbar", "hfit_ls"):
             H = torch.full((r, n), 1.0 / r, dtype=torch.float32, device=V.device)
         else:
             raise ValueError(f"unknown start {start!r}")
         ctx = nmf.Nmf(V, W, H, precision=precision, tol_kind="gap", tol=tol,
                       check_every=check_every)
-        if start == "net_ls":
+        if start == "hfit_ls":
+            for _ in range(hfit):
+                ctx.update_h()
+        if start in ("net_ls", "hfit_ls"):
             ctx.refit_w(ls_floor)
     conv, iters, f, _ = ctx.solve(max_iters)
     _sync()
