@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -46,17 +47,27 @@ __device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
 }
 
 constexpr int kThreads = 256;
-constexpr int S = 3;          // copy-ring stages in flight
 constexpr int kMaxNB = 128;
 constexpr int kMaxMB = 128;
-constexpr int kLdsBytes = S * (kMaxMB + 64) * 128;  // 72 KB: two workgroups per CU
-static_assert((kMaxMB * 68 + 64 * 68) * 4 <= kLdsBytes, "phase W epilogue fits");
-static_assert((64 * (kMaxNB + 16) + 64 * 80) * 4 <= kLdsBytes, "phase H epilogue fits");
+constexpr int kStageBytes = (kMaxMB + 64) * 128;  // largest copy-ring stage
+// Copy-ring depth: 3 stages (72 KB of LDS) with two workgroups per CU, 5
+// stages (120 KB) with one.
+constexpr int kLdsBytes3 = 3 * kStageBytes, kLdsBytes5 = 5 * kStageBytes;
+static_assert((kMaxMB * 68 + 64 * 68) * 4 <= kLdsBytes3, "phase W epilogue fits");
+static_assert((64 * (kMaxNB + 16) + 64 * 80) * 4 <= kLdsBytes3, "phase H epilogue fits");
 
-// The persistent kernel's LDS: the copy ring during a tile's product, then
+// The persistent kernels' LDS: the copy ring during a tile's product, then
 // the tile's epilogue.  At namespace scope so that the out-of-line tile
-// functions address it directly (as LDS, not through generic pointers).
-__shared__ __attribute__((aligned(1024))) char g_lds[kLdsBytes];
+// functions address it directly (as LDS, not through generic pointers); each
+// kernel allocates only the array its tile functions use.
+__shared__ __attribute__((aligned(1024))) char g_lds3[kLdsBytes3];
+__shared__ __attribute__((aligned(1024))) char g_lds5[kLdsBytes5];
+template <int S>
+__device__ __forceinline__ char* lds_base() {
+  static_assert(S == 3 || S == 5, "ring depth");
+  if constexpr (S == 3) return g_lds3;
+  else return g_lds5;
+}
 
 // A wait longer than this many ticks of the 100 MHz constant clock (2 s)
 // means the schedule is broken: raise the error flag and leave.
@@ -84,30 +95,97 @@ struct Prob {
   int32_t kw, kh;       // 32-float stages along n (phase W) and along p (phase H)
 };
 
-// Counter block, cleared before every launch: [0] queue head, [32] error
-// flag of this launch, then 4 per problem from kCtrBase: W arrivals, W
+// Counter block, cleared before every launch: [0] error flag of this launch;
+// for each queue q, [kHeadBase + 32 q] its head and [kHeadBase + 32 q + 1]
+// its completed tiles; then 4 per problem from kCtrBase: W arrivals, W
 // phases done, H arrivals, H phases done.  One more word after the block
 // keeps the error flag across launches until the host reads and clears it.
-constexpr int kCtrErr = 32;
-constexpr int kCtrBase = 64;
+constexpr int kMaxQueues = 16;
+constexpr int kCtrErr = 0;
+constexpr int kHeadBase = 32;
+constexpr int kCtrBase = kHeadBase + 32 * kMaxQueues;
+
+// One tile queue: its schedule starts at sched[off] and holds per_iter
+// tiles per iteration.
+struct QInfo {
+  uint32_t off, per_iter;
+};
 
 namespace {
 
-__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// s_waitcnt vmcnt(VM) (gfx9 encoding, vmcnt split over bits 3:0 and
+// 15:14), leaving expcnt and lgkmcnt unconstrained.
+template <int VM>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(VM >= 0 && VM < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((VM & 0xF) | (0x7 << 4) | (0xF << 8) | (((VM >> 4) & 0x3) << 14));
 }
 
-// Thread 0 waits until *c >= target (bounded); the workgroup learns whether
-// the wait succeeded.  Afterwards every wave acquires at agent scope so that
-// its loads see what the producers released.
+// Coherence of the data tiles pass to each other (factors, W^T, Grams,
+// partial Grams).  Every access to it is device-scope: loads and stores are
+// relaxed agent-scope atomics (sc1: served at the device's coherence point,
+// not from a compute unit's L1 or a non-coherent L2 line), and the copy ring
+// reads these operands with the same cache policy.  A producer's stores are
+// therefore visible device-wide once its vmcnt has drained, which every wave
+// waits for before thread 0 advances the counter that publishes the tile; a
+// consumer issues its loads only after it has seen that counter.  V and V^T,
+// which no tile writes, are read through the caches as usual, and no
+// whole-cache write-back or invalidation is needed anywhere.
+__device__ __forceinline__ uint32_t ld_counter(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float2 ld2_dev(const float* p) {  // 8-byte aligned
+  const uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+}
+__device__ __forceinline__ float4 ld4_dev(const float* p) {  // 8-byte aligned
+  const float2 a = ld2_dev(p), b = ld2_dev(p + 2);
+  return make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ float ld1_dev(const float* p) {
+  return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st2_dev(float* p, float a, float b) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p),
+                     (uint64_t)__float_as_uint(a) | ((uint64_t)__float_as_uint(b) << 32),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st4_dev(float* p, float4 v) {
+  st2_dev(p, v.x, v.y);
+  st2_dev(p + 2, v.z, v.w);
+}
+__device__ __forceinline__ void st1_dev(float* p, float v) {
+  __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+// 4 consecutive floats of row `row`, columns col..col+3 (device scope), zero
+// outside [0, rows) x [0, cols); ld and col multiples of 2.
+__device__ __forceinline__ float4 ld4m_dev(const float* p, int64_t ld, int64_t row, int64_t rows,
+                                           int64_t col, int64_t cols) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (row >= rows) return v;
+  const float* q = p + row * ld + col;
+  if (col + 3 < cols) return ld4_dev(q);
+  if (col + 0 < cols) v.x = ld1_dev(q);
+  if (col + 1 < cols) v.y = ld1_dev(q + 1);
+  if (col + 2 < cols) v.z = ld1_dev(q + 2);
+  return v;
+}
+
+// Thread 0 waits until *c >= target (bounded); the barrier orders every
+// wave's later loads after that observation.  The workgroup learns whether
+// the wait succeeded.
 __device__ bool wait_geq(const uint32_t* c, uint32_t target, uint32_t* ctr, uint32_t* sticky,
                          int* s_flag) {
   if (threadIdx.x == 0) {
     int ok = 1;
-    if (ld_acquire(c) < target) {
+    if (ld_counter(c) < target) {
       const uint64_t t0 = wall_clock64();
-      while (ld_acquire(c) < target) {
-        if (ld_acquire(ctr + kCtrErr)) {
+      while (ld_counter(c) < target) {
+        if (ld_counter(ctr + kCtrErr)) {
           ok = 0;
           break;
         }
@@ -123,48 +201,66 @@ __device__ bool wait_geq(const uint32_t* c, uint32_t target, uint32_t* ctr, uint
     *s_flag = ok;
   }
   __syncthreads();
-  const bool ok = *s_flag != 0;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok;
+  return *s_flag != 0;
 }
 
-// Publish the tile (all of its global writes) and count its arrival; the
-// last arrival of the phase sums the partial Grams and marks the phase done.
+// Publish the tile and count its arrival; the last arrival of the phase sums
+// the partial Grams (device-scope loads, ascending tile order) and marks the
+// phase done.  Every wave first waits for its own device-scope stores to
+// complete; after the barrier thread 0 advances the arrival counter.
 __device__ void finish_tile(const Prob& P, int tiles, uint32_t iter, uint32_t* arr,
                             uint32_t* done, float* G, int* s_flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  wait_vm<0>();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t old =
-        __hip_atomic_fetch_add(arr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t old = __hip_atomic_fetch_add(arr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *s_flag = (old + 1 == (iter + 1) * (uint32_t)tiles);
   }
   __syncthreads();
   if (!*s_flag) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  const int rp = P.rp, elems = rp * rp;
-  // thread e sums partials q = 0, 1, ... in order for its elements; the
-  // elements' loads of one q are independent, so they are all in flight
-  constexpr int U = 16;  // 64 * 64 / 256 elements per thread at most
-  float s[U];
+  // G[e] = sum_q part[q][e]: each thread owns up to 8 float pairs of G and
+  // reads 4 partials per round (32 independent 8-byte loads)
+  const int rp = P.rp, e2n = rp * rp / 2;
+  float2 acc[8];
 #pragma unroll
-  for (int u = 0; u < U; ++u) s[u] = 0.f;
-  for (int q = 0; q < tiles; ++q) {
-    const float* part = P.gpart + (int64_t)q * elems;
+  for (int u = 0; u < 8; ++u) acc[u] = make_float2(0.f, 0.f);
+  int q = 0;
+  for (; q + 3 < tiles; q += 4) {
+    float2 v[4][8];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = threadIdx.x + kThreads * u;
-      if (e < elems) s[u] += part[e];
+    for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e2 = threadIdx.x + kThreads * u;
+        v[qq][u] = e2 < e2n ? ld2_dev(P.gpart + ((int64_t)(q + qq) * e2n + e2) * 2)
+                            : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        acc[u].x += v[qq][u].x;
+        acc[u].y += v[qq][u].y;
+      }
+  }
+  for (; q < tiles; ++q)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e2 = threadIdx.x + kThreads * u;
+      if (e2 < e2n) {
+        const float2 v = ld2_dev(P.gpart + ((int64_t)q * e2n + e2) * 2);
+        acc[u].x += v.x;
+        acc[u].y += v.y;
+      }
     }
-  }
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int e = threadIdx.x + kThreads * u;
-    if (e < elems) G[e] = s[u];
+  for (int u = 0; u < 8; ++u) {
+    const int e2 = threadIdx.x + kThreads * u;
+    if (e2 < e2n) st2_dev(G + 2 * e2, acc[u].x, acc[u].y);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  wait_vm<0>();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(done, iter + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(done, iter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // 4 consecutive floats of row `row`, columns col..col+3, zero outside
@@ -186,6 +282,7 @@ __device__ __forceinline__ float4 lds4(const float* p) {
   return *reinterpret_cast<const float4*>(p);
 }
 
+
 // ---------------------------------------------------------------------------
 // The product of a tile, C[m][c] = sum_k X[m][k] Y[c][k] (m < MB = 64 MS,
 // c < RPY = 32 or 64 rows of Y), both operands contiguous along k and zero
@@ -200,14 +297,6 @@ __device__ __forceinline__ float4 lds4(const float* p) {
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-// s_waitcnt vmcnt(VM) (gfx9 encoding, vmcnt split over bits 3:0 and
-// 15:14), leaving expcnt and lgkmcnt unconstrained.
-template <int VM>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(VM >= 0 && VM < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((VM & 0xF) | (0x7 << 4) | (0xF << 8) | (((VM >> 4) & 0x3) << 14));
-}
-
 // Barrier for the ring: a __syncthreads() would also wait for every
 // outstanding copy (they are counted by vmcnt); this one retires the wave's
 // own LDS reads and meets at a bare s_barrier.  The asm statements keep the
@@ -218,14 +307,14 @@ __device__ __forceinline__ void ring_barrier() {
   asm volatile("" ::: "memory");
 }
 
-template <int MS, int NT>
+template <int S, int MS, int NT>
 __device__ __forceinline__ void ring_nt(const float* __restrict__ X, int64_t ldx,
                                         const float* __restrict__ Y, int64_t ldy, int nst,
                                         char* lds, v4f (&acc)[MS][NT]) {
   constexpr int MB = 64 * MS, RPY = (NT <= 2) ? 32 : 64, ROWS = MB + RPY;
   constexpr int L = ROWS / 32;  // copy instructions per wave per stage
   constexpr int STAGE = ROWS * 128;
-  static_assert(ROWS % 32 == 0 && S * STAGE <= kLdsBytes, "stage layout");
+  static_assert(ROWS % 32 == 0 && STAGE <= kStageBytes, "stage layout");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c = lane & 15, g = lane >> 4;
   // lane's source in copy j: stage row rr = 8 (wave L + j) + lane / 8, slot
   // lane % 8, holding chunk (lane % 8) ^ (rr % 8) = (lane % 8) ^ (lane / 8)
@@ -237,12 +326,17 @@ __device__ __forceinline__ void ring_nt(const float* __restrict__ X, int64_t ldx
     src[j] = rr < MB ? reinterpret_cast<const char*>(X + rr * ldx) + 16 * chunk
                      : reinterpret_cast<const char*>(Y + (rr - MB) * ldy) + 16 * chunk;
   }
+  // copy j of this wave carries 8 rows of X (cached) or of Y (device-scope
+  // reads: the Y operands are written by other tiles)
   auto issue = [&](int st) {
     char* dst = lds + (st % S) * STAGE;
 #pragma unroll
-    for (int j = 0; j < L; ++j)
-      __builtin_amdgcn_global_load_lds(static_cast<const void*>(src[j] + (int64_t)st * 128),
-                                       (lds_ptr_t)(dst + (wave * L + j) * 1024), 16, 0, 0);
+    for (int j = 0; j < L; ++j) {
+      const void* sp = static_cast<const void*>(src[j] + (int64_t)st * 128);
+      lds_ptr_t dp = (lds_ptr_t)(dst + (wave * L + j) * 1024);
+      if (8 * (wave * L + j) < MB) __builtin_amdgcn_global_load_lds(sp, dp, 16, 0, 0);
+      else __builtin_amdgcn_global_load_lds(sp, dp, 16, 0, 16);
+    }
   };
 #pragma unroll
   for (int a = 0; a < MS; ++a)
@@ -269,14 +363,18 @@ __device__ __forceinline__ void ring_nt(const float* __restrict__ X, int64_t ldx
     }
   };
   // Stage st lives in buffer st % S.  At the top of iteration st, stages st
-  // and (if it exists) st + 1 have been issued; once this wave's copies of
-  // stage st have landed, one barrier certifies that every wave's copies of
-  // stage st are in LDS and that every wave has finished computing stage
-  // st - 1, whose buffer is then refilled with stage st + 2.
+  // .. min(st + S - 2, nst - 1) have been issued; once this wave's copies of
+  // stage st have landed (at most L copies per later stage outstanding), one
+  // barrier certifies that every wave's copies of stage st are in LDS and
+  // that every wave has finished computing stage st - 1, whose buffer is
+  // then refilled with stage st + S - 1.
   const int pre = nst < S - 1 ? nst : S - 1;
   for (int st = 0; st < pre; ++st) issue(st);
   for (int st = 0; st < nst; ++st) {
-    if (st + 1 < nst) wait_vm<L>();
+    const int later = nst - 1 - st;
+    if (S >= 5 && later >= 3) wait_vm<(S >= 5 ? 3 * L : 0)>();
+    else if (S >= 4 && later >= 2) wait_vm<(S >= 4 ? 2 * L : 0)>();
+    else if (later >= 1) wait_vm<L>();
     else wait_vm<0>();
     ring_barrier();
     if (st + S - 1 < nst) issue(st + S - 1);
@@ -288,30 +386,46 @@ __device__ __forceinline__ void ring_nt(const float* __restrict__ X, int64_t ldx
 // ---------------------------------------------------------------------------
 // Phase W tile t: rows [t MB, t MB + MB) of V, K = n.
 // ---------------------------------------------------------------------------
-template <int MS, int NT>
+template <int S, int MS, int NT>
 __device__ __attribute__((noinline)) void tile_w(const Prob& P, int t) {
   constexpr int MB = 64 * MS, RP = 16 * NT;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, c = lane & 15, g = lane >> 4;
   const int64_t p0 = (int64_t)t * MB;
   const int64_t p = P.p;
+  // the epilogue's inputs (the tile's W rows and G_H), loaded while the
+  // product runs
+  constexpr int NWP = MB * (RP / 4) / kThreads;
+  constexpr int NGP = (RP * (RP / 4) + kThreads - 1) / kThreads;
+  static_assert(MB * (RP / 4) % kThreads == 0, "W rows split evenly");
+  float4 wpre[NWP], gpre[NGP];
+#pragma unroll
+  for (int u = 0; u < NWP; ++u) {
+    const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
+    wpre[u] = (p0 + row < p) ? ld4_dev(&P.Wp[(p0 + row) * RP + 4 * q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int u = 0; u < NGP; ++u) {
+    const int idx = tid + kThreads * u;
+    gpre[u] = idx < RP * (RP / 4) ? ld4_dev(&P.GH[4 * idx]) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   v4f acc[MS][NT];
-  ring_nt<MS, NT>(P.V + p0 * P.ldv, P.ldv, P.Hp, P.ldh, P.kw, g_lds, acc);
-  float* lds = reinterpret_cast<float*>(g_lds);
+  ring_nt<S, MS, NT>(P.V + p0 * P.ldv, P.ldv, P.Hp, P.ldh, P.kw, lds_base<S>(), acc);
+  float* lds = reinterpret_cast<float*>(lds_base<S>());
   const int wrow = 16 * MS * wv;
 
   // ---- epilogue: B = W_rows G_H, W <- W * (A / B), W^T, partial Gram -----
   constexpr int PS = RP + 4;
   float* Ws = lds;                // [MB][PS]
   float* Gs = lds + kMaxMB * 68;  // [RP][PS]
-  for (int idx = tid; idx < MB * (RP / 4); idx += kThreads) {
-    const int row = idx / (RP / 4), q = idx % (RP / 4);
-    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (p0 + row < p) w = lds4(&P.Wp[(p0 + row) * RP + 4 * q]);
-    st4(&Ws[row * PS + 4 * q], w);
+#pragma unroll
+  for (int u = 0; u < NWP; ++u) {
+    const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
+    st4(&Ws[row * PS + 4 * q], wpre[u]);
   }
-  for (int idx = tid; idx < RP * (RP / 4); idx += kThreads) {
-    const int row = idx / (RP / 4), q = idx % (RP / 4);
-    st4(&Gs[row * PS + 4 * q], lds4(&P.GH[row * RP + 4 * q]));
+#pragma unroll
+  for (int u = 0; u < NGP; ++u) {
+    const int idx = tid + kThreads * u;
+    if (idx < RP * (RP / 4)) st4(&Gs[(4 * idx / RP) * PS + 4 * idx % RP], gpre[u]);
   }
   __syncthreads();
   v4f den[MS][NT];
@@ -357,18 +471,18 @@ __device__ __attribute__((noinline)) void tile_w(const Prob& P, int t) {
   __syncthreads();
   for (int idx = tid; idx < MB * (RP / 4); idx += kThreads) {
     const int row = idx / (RP / 4), q = idx % (RP / 4);
-    if (p0 + row < p) st4(&P.Wp[(p0 + row) * RP + 4 * q], lds4(&Ws[row * PS + 4 * q]));
+    if (p0 + row < p) st4_dev(&P.Wp[(p0 + row) * RP + 4 * q], lds4(&Ws[row * PS + 4 * q]));
   }
   // W^T (RP x ldwt), the operand of the phase-H products: 4 rows of W per store
   for (int idx = tid; idx < RP * (MB / 4); idx += kThreads) {
-    const int k = idx / (MB / 4), r0 = 4 * (idx % (MB / 4));
+    const int k = idx % RP, r0 = 4 * (idx / RP);  // k fastest: conflict-free LDS reads
     float* dst = P.WT + (int64_t)k * P.ldwt + p0 + r0;
     if (p0 + r0 + 3 < p) {
-      st4(dst, make_float4(Ws[r0 * PS + k], Ws[(r0 + 1) * PS + k], Ws[(r0 + 2) * PS + k],
-                           Ws[(r0 + 3) * PS + k]));
+      st4_dev(dst, make_float4(Ws[r0 * PS + k], Ws[(r0 + 1) * PS + k], Ws[(r0 + 2) * PS + k],
+                               Ws[(r0 + 3) * PS + k]));
     } else {
       for (int e = 0; e < 4; ++e)
-        if (p0 + r0 + e < p) dst[e] = Ws[(r0 + e) * PS + k];
+        if (p0 + r0 + e < p) st1_dev(dst + e, Ws[(r0 + e) * PS + k]);
     }
   }
   // partial Gram C[i][j] = sum_m Wn[m][i] Wn[m][j] over the tile's rows
@@ -380,14 +494,14 @@ __device__ __attribute__((noinline)) void tile_w(const Prob& P, int t) {
     for (int m0 = 0; m0 < MB; m0 += 4)
       cg = mfma(Ws[(m0 + g) * PS + 16 * it + c], Ws[(m0 + g) * PS + 16 * jt + c], cg);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) gp[(16 * it + 4 * g + v) * RP + 16 * jt + c] = cg[v];
+    for (int v = 0; v < 4; ++v) st1_dev(&gp[(16 * it + 4 * g + v) * RP + 16 * jt + c], cg[v]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Phase H tile t: columns [t NB, t NB + NB) of V (rows of V^T), K = p.
 // ---------------------------------------------------------------------------
-template <int MS, int NT>
+template <int S, int MS, int NT>
 __device__ __attribute__((noinline)) void tile_h(const Prob& P, int t) {
   constexpr int NB = 64 * MS, RP = 16 * NT;
   constexpr int PV = NB + 16;
@@ -395,21 +509,32 @@ __device__ __attribute__((noinline)) void tile_h(const Prob& P, int t) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, c = lane & 15, g = lane >> 4;
   const int64_t j0 = (int64_t)t * NB;
   const int64_t n = P.n;
+  // the epilogue's inputs (the tile's H columns), loaded while the product
+  // runs; G_W is written by the phase-W tiles and read after the product
+  constexpr int NHP = RP * (NB / 4) / kThreads;
+  static_assert(RP * (NB / 4) % kThreads == 0, "H columns split evenly");
+  float4 hpre[NHP];
+#pragma unroll
+  for (int u = 0; u < NHP; ++u) {
+    const int idx = tid + kThreads * u, row = idx / (NB / 4), q = idx % (NB / 4);
+    hpre[u] = ld4m_dev(P.Hp, P.ldh, row, RP, j0 + 4 * q, n);
+  }
   v4f acc[MS][NT];
-  ring_nt<MS, NT>(P.VT + j0 * P.ldvt, P.ldvt, P.WT, P.ldwt, P.kh, g_lds, acc);
-  float* lds = reinterpret_cast<float*>(g_lds);
+  ring_nt<S, MS, NT>(P.VT + j0 * P.ldvt, P.ldvt, P.WT, P.ldwt, P.kh, lds_base<S>(), acc);
+  float* lds = reinterpret_cast<float*>(lds_base<S>());
   const int wcol = 16 * MS * wv;
 
   // ---- epilogue: D^T = H_cols^T G_W, H <- H * (S / D), partial Gram ------
   float* Hs = lds;                       // [RP][PV]
   float* Gs = lds + 64 * (kMaxNB + 16);  // [RP][PR]
-  for (int idx = tid; idx < RP * (NB / 4); idx += kThreads) {
-    const int row = idx / (NB / 4), q = idx % (NB / 4);
-    st4(&Hs[row * PV + 4 * q], ld4(P.Hp, P.ldh, row, RP, j0 + 4 * q, n));
+#pragma unroll
+  for (int u = 0; u < NHP; ++u) {
+    const int idx = tid + kThreads * u, row = idx / (NB / 4), q = idx % (NB / 4);
+    st4(&Hs[row * PV + 4 * q], hpre[u]);
   }
   for (int idx = tid; idx < RP * (RP / 4); idx += kThreads) {
     const int row = idx / (RP / 4), q = idx % (RP / 4);
-    st4(&Gs[row * PR + 4 * q], lds4(&P.GW[row * RP + 4 * q]));
+    st4(&Gs[row * PR + 4 * q], ld4_dev(&P.GW[row * RP + 4 * q]));
   }
   __syncthreads();
   v4f den[MS][NT];
@@ -452,7 +577,7 @@ __device__ __attribute__((noinline)) void tile_h(const Prob& P, int t) {
   // are padded to a multiple of 32 columns, so whole float4s are stored
   for (int idx = tid; idx < RP * (NB / 4); idx += kThreads) {
     const int row = idx / (NB / 4), q = idx % (NB / 4);
-    if (j0 + 4 * q < n) st4(&P.Hp[row * P.ldh + j0 + 4 * q], lds4(&Hs[row * PV + 4 * q]));
+    if (j0 + 4 * q < n) st4_dev(&P.Hp[row * P.ldh + j0 + 4 * q], lds4(&Hs[row * PV + 4 * q]));
   }
   // partial Gram C[i][j] = sum_m Hn[i][m] Hn[j][m] over the tile's columns
   float* gp = P.gpart + (int64_t)t * RP * RP;
@@ -469,40 +594,57 @@ __device__ __attribute__((noinline)) void tile_h(const Prob& P, int t) {
       cg = mfma(a.w, b.w, cg);
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) gp[(16 * it + 4 * g + v) * RP + 16 * jt + c] = cg[v];
+    for (int v = 0; v < 4; ++v) st1_dev(&gp[(16 * it + 4 * g + v) * RP + 16 * jt + c], cg[v]);
   }
 }
 
 #define NMFB_CASES(X) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 1) X(2, 2) X(2, 3) X(2, 4)
 
-// The persistent kernel.  sched holds one iteration's tiles, each coded as
-// problem << 17 | phase << 16 | tile; entry e of iteration i is queue slot
-// i * per_iter + e.
-__global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __restrict__ probs,
-                                                               const uint32_t* __restrict__ sched,
-                                                               uint32_t per_iter, uint32_t total,
-                                                               uint32_t* __restrict__ ctr,
-                                                               uint32_t* __restrict__ sticky) {
+// The persistent loop.  Queue q's schedule holds one iteration's tiles, each
+// coded as problem << 17 | phase << 16 | tile; entry e of iteration i is
+// queue slot i * per_iter + e.  With per-XCD queues (`local`) a workgroup
+// serves the queue of the XCD it runs on (hardware register XCC_ID), so a
+// problem's tiles share one L2 for the operands they read through the cache;
+// a workgroup on an XCD without a queue leaves at once (the host's check of
+// the completed tiles reports any queue nobody served).
+__device__ __forceinline__ uint32_t xcc_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v & 0xF;
+}
+
+template <int S>
+__device__ __forceinline__ void persistent_loop(const Prob* __restrict__ probs,
+                                                const uint32_t* __restrict__ sched,
+                                                const QInfo* __restrict__ queues, int nq,
+                                                uint32_t iters, int local,
+                                                uint32_t* __restrict__ ctr,
+                                                uint32_t* __restrict__ sticky) {
   __shared__ uint32_t s_slot;
   __shared__ int s_flag;
+  const int q = local ? (int)xcc_id() : 0;
+  if (q >= nq) return;
+  const uint32_t per_iter = queues[q].per_iter, total = iters * per_iter;
+  const uint32_t* qs = sched + queues[q].off;
+  uint32_t* head = ctr + kHeadBase + 32 * q;
   for (;;) {
     if (threadIdx.x == 0)
-      s_slot = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_slot = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const uint32_t slot = s_slot;
     __syncthreads();
     if (slot >= total) break;
     const uint32_t iter = slot / per_iter;
-    const uint32_t code = __builtin_amdgcn_readfirstlane(sched[slot % per_iter]);
+    const uint32_t code = __builtin_amdgcn_readfirstlane(qs[slot % per_iter]);
     const int b = (int)(code >> 17), phase = (int)((code >> 16) & 1), t = (int)(code & 0xffff);
     const Prob& P = probs[b];  // uniform: read with scalar loads, never copied
     uint32_t* pc = ctr + kCtrBase + 4 * b;
     if (phase == 0) {
-      if (!wait_geq(pc + 3, iter, ctr, sticky, &s_flag)) break;  // H phase of iteration - 1
+      if (!wait_geq(pc + 3, iter, ctr, sticky, &s_flag)) break;  // H of iteration - 1
       switch (P.msw * 8 + P.rp / 16) {
 #define CASE_W(MS, NT) \
   case MS * 8 + NT:    \
-    tile_w<MS, NT>(P, t); \
+    tile_w<S, MS, NT>(P, t); \
     break;
         NMFB_CASES(CASE_W)
 #undef CASE_W
@@ -510,11 +652,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __
       }
       finish_tile(P, P.tilesW, iter, pc + 0, pc + 1, P.GW, &s_flag);
     } else {
-      if (!wait_geq(pc + 1, iter + 1, ctr, sticky, &s_flag)) break;  // W phase of this iteration
+      if (!wait_geq(pc + 1, iter + 1, ctr, sticky, &s_flag)) break;  // W of this iteration
       switch (P.msh * 8 + P.rp / 16) {
 #define CASE_H(MS, NT) \
   case MS * 8 + NT:    \
-    tile_h<MS, NT>(P, t); \
+    tile_h<S, MS, NT>(P, t); \
     break;
         NMFB_CASES(CASE_H)
 #undef CASE_H
@@ -522,8 +664,43 @@ __global__ __launch_bounds__(kThreads, 2) void k_batch_persistent(const Prob* __
       }
       finish_tile(P, P.tilesH, iter, pc + 2, pc + 3, P.GH, &s_flag);
     }
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(head + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
+}
+
+// Two workgroups per CU, 3-stage rings.
+__global__ __launch_bounds__(kThreads, 2) void k_batch_persistent3(
+    const Prob* __restrict__ probs, const uint32_t* __restrict__ sched,
+    const QInfo* __restrict__ queues, int nq, uint32_t iters, int local,
+    uint32_t* __restrict__ ctr, uint32_t* __restrict__ sticky) {
+  persistent_loop<3>(probs, sched, queues, nq, iters, local, ctr, sticky);
+}
+
+// One workgroup per CU, 5-stage rings.
+__global__ __launch_bounds__(kThreads, 1) void k_batch_persistent5(
+    const Prob* __restrict__ probs, const uint32_t* __restrict__ sched,
+    const QInfo* __restrict__ queues, int nq, uint32_t iters, int local,
+    uint32_t* __restrict__ ctr, uint32_t* __restrict__ sticky) {
+  persistent_loop<5>(probs, sched, queues, nq, iters, local, ctr, sticky);
+}
+
+// After a launch: every queue must have completed all of its tiles (a
+// queue whose XCD ran none of the workgroups would not have); otherwise
+// raise the error flags.
+__global__ void k_batch_verify(const QInfo* __restrict__ queues, int nq, uint32_t iters,
+                               uint32_t* __restrict__ ctr, uint32_t* __restrict__ sticky) {
+  const int q = threadIdx.x;
+  if (q < nq && ctr[kHeadBase + 32 * q + 1] != iters * queues[q].per_iter) {
+    atomicOr(ctr + kCtrErr, 1u);
+    atomicOr(sticky, 1u);
+  }
+}
+
+// XCC_ID of every workgroup of a grid (host check of the XCD-local mode).
+__global__ void k_batch_xcc_probe(uint32_t* __restrict__ out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 // Set-up and copy kernels (grid.y = problem).
@@ -706,7 +883,10 @@ struct nmf_batch {
   uint32_t* ctr = nullptr;
   int64_t nctr = 0;
   uint32_t* sched = nullptr;
-  uint32_t per_iter = 0;
+  nmfb::QInfo* dq = nullptr;        // queue table (device)
+  std::vector<nmfb::QInfo> queues;  // host copy
+  int local = 0;                    // XCD-local queues (else one global queue)
+  int nq = 1;
   int4* obj_tiles = nullptr;
   int64_t nobj = 0;
   int64_t* obj_first = nullptr;
@@ -747,14 +927,16 @@ bool table_ok(const int32_t* t) {
 
 // Apply the table to the descriptors and rebuild the schedule.
 nmf_status plan(nmf_batch* b) {
-  std::vector<uint32_t> w, h;
-  // problems in decreasing order of work, so that large tiles start early
+  // problems in decreasing order of work, so that large tiles start early;
+  // in the XCD-local mode each problem goes to the queue with the least work
+  // so far (largest first)
   std::vector<int> order(b->count);
   for (int i = 0; i < b->count; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    const Prob &a = b->host[x], &c = b->host[y];
-    return (int64_t)a.p * a.n * a.rp > (int64_t)c.p * c.n * c.rp;
-  });
+  auto work = [&](int i) {
+    const Prob& a = b->host[i];
+    return (int64_t)a.p * a.n * a.rp;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
   for (int i = 0; i < b->count; ++i) {
     Prob& P = b->host[i];
     const int cls = P.rp / 16 - 1;
@@ -764,38 +946,92 @@ nmf_status plan(nmf_batch* b) {
     P.tilesH = (int32_t)((P.n + 64 * P.msh - 1) / (64 * P.msh));
     if (P.tilesW > 65535 || P.tilesH > 65535) return NMF_EUNSUPPORTED;
   }
+  std::vector<std::vector<int>> members(b->nq);
+  std::vector<int64_t> load(b->nq, 0);
   for (int i : order) {
-    const Prob& P = b->host[i];
-    for (int t = 0; t < P.tilesW; ++t) w.push_back(((uint32_t)i << 17) | (uint32_t)t);
+    const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    members[q].push_back(i);
+    load[q] += work(i);
   }
-  for (int i : order) {
-    const Prob& P = b->host[i];
-    for (int t = 0; t < P.tilesH; ++t) h.push_back(((uint32_t)i << 17) | (1u << 16) | (uint32_t)t);
+  std::vector<uint32_t> all;
+  b->queues.assign(b->nq, QInfo{0, 0});
+  for (int q = 0; q < b->nq; ++q) {
+    b->queues[q].off = (uint32_t)all.size();
+    for (int i : members[q])
+      for (int t = 0; t < b->host[i].tilesW; ++t) all.push_back(((uint32_t)i << 17) | (uint32_t)t);
+    for (int i : members[q])
+      for (int t = 0; t < b->host[i].tilesH; ++t)
+        all.push_back(((uint32_t)i << 17) | (1u << 16) | (uint32_t)t);
+    b->queues[q].per_iter = (uint32_t)all.size() - b->queues[q].off;
   }
-  w.insert(w.end(), h.begin(), h.end());
   if (b->sched) (void)hipFree(b->sched);
   b->sched = nullptr;
-  BTRY_HIP(hipMalloc(&b->sched, w.size() * sizeof(uint32_t)));
-  BTRY_HIP(hipMemcpyAsync(b->sched, w.data(), w.size() * sizeof(uint32_t), hipMemcpyHostToDevice, b->st));
+  BTRY_HIP(hipMalloc(&b->sched, std::max<size_t>(1, all.size()) * sizeof(uint32_t)));
+  BTRY_HIP(hipMemcpyAsync(b->sched, all.data(), all.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, b->st));
+  BTRY_HIP(hipMemcpyAsync(b->dq, b->queues.data(), b->nq * sizeof(QInfo), hipMemcpyHostToDevice,
+                          b->st));
   BTRY_HIP(hipMemcpyAsync(b->dprobs, b->host.data(), b->host.size() * sizeof(Prob),
                           hipMemcpyHostToDevice, b->st));
   BTRY_HIP(hipStreamSynchronize(b->st));
-  b->per_iter = (uint32_t)w.size();
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   b->graph = nullptr;
   b->graph_iters = 0;
   return NMF_OK;
 }
 
+// XCD-local mode if the XCC_ID register partitions a persistent grid into
+// nq <= kMaxQueues equal groups numbered 0 .. nq - 1 (else one global queue).
+// NMF_BATCH_QUEUES=1 in the environment forces the global queue.
+nmf_status choose_queues(nmf_batch* b) {
+  b->local = 0;
+  b->nq = 1;
+  const char* env = std::getenv("NMF_BATCH_QUEUES");
+  if (env && std::strcmp(env, "1") == 0) return NMF_OK;
+  const int grid = 2 * b->cus;
+  uint32_t* d = nullptr;
+  BTRY_HIP(hipMalloc(&d, grid * sizeof(uint32_t)));
+  std::vector<uint32_t> h(grid, 0xffffffffu);
+  hipLaunchKernelGGL(k_batch_xcc_probe, dim3(grid), dim3(64), 0, b->st, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, grid * sizeof(uint32_t), hipMemcpyDeviceToHost, b->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+  (void)hipFree(d);
+  if (e != hipSuccess) return NMF_EDEVICE;
+  int cnt[kMaxQueues] = {0};
+  for (uint32_t v : h) {
+    if (v >= (uint32_t)kMaxQueues) return NMF_OK;
+    ++cnt[v];
+  }
+  int nq = 0;
+  while (nq < kMaxQueues && cnt[nq] > 0) ++nq;
+  for (int q = nq; q < kMaxQueues; ++q)
+    if (cnt[q]) return NMF_OK;  // ids not contiguous from 0
+  for (int q = 0; q < nq; ++q)
+    if (cnt[q] != cnt[0]) return NMF_OK;  // unequal groups
+  if (nq > 1) {
+    b->local = 1;
+    b->nq = nq;
+  }
+  return NMF_OK;
+}
+
 nmf_status enqueue_steps(nmf_batch* b, int32_t iters, hipStream_t s) {
-  const uint64_t total = (uint64_t)iters * b->per_iter;
-  if (total >= 0xffffffffull) return NMF_EUNSUPPORTED;
+  for (const QInfo& q : b->queues)
+    if ((uint64_t)iters * q.per_iter >= 0xffffffffull) return NMF_EUNSUPPORTED;
   hipLaunchKernelGGL(k_batch_fill, dim3((unsigned)std::min<int64_t>(64, (b->nctr + 255) / 256)),
                      dim3(256), 0, s, b->ctr, b->nctr);
   BTRY_HIP(hipGetLastError());
   const unsigned grid = (unsigned)(b->cus * b->table[8]);
-  hipLaunchKernelGGL(k_batch_persistent, dim3(grid), dim3(kThreads), 0, s, b->dprobs, b->sched,
-                     b->per_iter, (uint32_t)total, b->ctr, b->ctr + b->nctr);
+  if (b->table[8] == 2)
+    hipLaunchKernelGGL(k_batch_persistent3, dim3(grid), dim3(kThreads), 0, s, b->dprobs, b->sched,
+                       b->dq, b->nq, (uint32_t)iters, b->local, b->ctr, b->ctr + b->nctr);
+  else
+    hipLaunchKernelGGL(k_batch_persistent5, dim3(grid), dim3(kThreads), 0, s, b->dprobs, b->sched,
+                       b->dq, b->nq, (uint32_t)iters, b->local, b->ctr, b->ctr + b->nctr);
+  BTRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_batch_verify, dim3(1), dim3(64), 0, s, b->dq, b->nq, (uint32_t)iters, b->ctr,
+                     b->ctr + b->nctr);
   BTRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_batch_store, dim3(64, (unsigned)b->count), dim3(256), 0, s, b->dprobs);
   BTRY_HIP(hipGetLastError());
@@ -965,6 +1201,9 @@ nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t c
       hipMemcpyAsync(b->obj_first, first.data(), first.size() * sizeof(int64_t),
                      hipMemcpyHostToDevice, b->st) != hipSuccess)
     return fail(NMF_EDEVICE);
+  if (hipMalloc(&b->dq, kMaxQueues * sizeof(QInfo)) != hipSuccess) return fail(NMF_ENOMEM);
+  s = choose_queues(b);
+  if (s != NMF_OK) return fail(s);
   s = plan(b);
   if (s != NMF_OK) return fail(s);
   hipLaunchKernelGGL(k_batch_pad, dim3(256, (unsigned)count), dim3(256), 0, b->st, b->dprobs);
@@ -1119,6 +1358,7 @@ void nmf_batch_destroy(nmf_batch* b) {
   if (b->dprobs) (void)hipFree(b->dprobs);
   if (b->ctr) (void)hipFree(b->ctr);
   if (b->sched) (void)hipFree(b->sched);
+  if (b->dq) (void)hipFree(b->dq);
   if (b->obj_tiles) (void)hipFree(b->obj_tiles);
   if (b->obj_first) (void)hipFree(b->obj_first);
   if (b->obj_part) (void)hipFree(b->obj_part);

@@ -213,3 +213,26 @@ def test_full_batched_workload(gpu_lib):
     for _, W, H in dev[::37]:
         assert torch.isfinite(W).all() and (W >= 0).all()
         assert torch.isfinite(H).all() and (H >= 0).all()
+
+
+def test_queue_modes_agree(gpu_lib, reference, monkeypatch):
+    """The XCD-local queues (each problem's tiles on one XCD, L1-only
+    coherence) and the single global queue (agent-scope release/acquire)
+    run the same tile arithmetic in the same reduction order: bit-identical
+    factors, both matching the oracle."""
+    from paper_1003_3272_amd import nmf
+    host, ref = reference
+    out = []
+    for mode in ("local", "global"):
+        if mode == "global":
+            monkeypatch.setenv("NMF_BATCH_QUEUES", "1")
+        else:
+            monkeypatch.delenv("NMF_BATCH_QUEUES", raising=False)
+        dev = _device(host)
+        with nmf.Batch(dev) as b:
+            b.step(10)
+            b.check()
+        out.append(dev)
+    for (_, W, H), (_, W2, H2) in zip(out[0], out[1]):
+        assert torch.equal(W, W2) and torch.equal(H, H2)
+    _check_10(out[0], ref, "local")
