@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--ldv-pad", type=int, default=0,
                     help="extra floats per V row in device memory (row-stride experiment)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-tier run")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="first copy 256 MiB between two device buffers (a plain copy kernel "
+                         "of known size, the reference for hardware byte counters)")
     ap.add_argument("--batch-iters", type=int, default=200)
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the time-to-tolerance experiment")
@@ -92,6 +95,28 @@ def _gen_matrix(args):
     Wb, m = args
     with threadpool_limits(1):
         return gen.warm_start_matrix(Wb, m)[0]
+
+
+def measured_traffic(stage, p, n, r, precision):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading
+    for a copy of known size), for the workload those counters were taken on;
+    None for any other workload or once the kernel source has changed."""
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "pmc_traffic_k_nt_dma_fp32_4096x16384_r64.md")
+    if (p, n, r, precision) != (4096, 16384, 64, "fp32") or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    src = os.path.join(here, "paper_1003_3272_amd", "csrc", "nmf_kernels.hip")
+    sha = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
+    val = re.search(rf"traffic_bytes_per_launch {stage}: ([0-9]+)", text)
+    if not sha or not val:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != sha.group(1):
+        return None
+    return int(val.group(1))
 
 
 def _gen_batch_problem(args):
@@ -283,6 +308,13 @@ def main():
     Hd = torch.from_numpy(H0).to(dev)
     stream = torch.cuda.current_stream()
 
+    if args.pmc_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = nmf.Nmf(Vd, Wd, Hd, precision=args.precision)
     f0 = ctx.objective()
     ctx.step(args.warmup)
@@ -318,7 +350,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, p, n, r, args.precision)
     roof["kernel"] = dom
     roof["kernel_ms"] = round(dom_ms, 4)
     roof["v_pass_gbs"] = round(vbytes / (dom_ms * 1e-3) / 1e9, 1)
