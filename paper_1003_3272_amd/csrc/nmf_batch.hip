@@ -77,18 +77,18 @@ constexpr uint64_t kWaitTicks = 200000000ull;
 
 // Per-problem descriptor (device copy; see the host builder for meaning).
 struct Prob {
-  float* V;      // padded copy of V: rows round_up(p, 128), pitch ldv = round_up(n, 32)
-  float* VT;     // padded V^T: rows round_up(n, 128), pitch ldvt = round_up(p, 32)
+  float* V;      // padded copy of V: rows round_up(p, 128), k to round_up(n, 32)
+  float* VT;     // padded V^T: rows round_up(n, 128), k to round_up(p, 32)
   const float* Vsrc;  // caller's V (read once, at creation)
   float* Wp;     // p x rp, pitch rp (working W, padded columns zero)
-  float* WT;     // W^T: rpy x ldwt (ldwt = round_up(p, 32)), padding zero
-  float* Hp;     // rpy x ldh (ldh = round_up(n, 32)), padded rows and columns zero
+  float* WT;     // W^T: rpy rows, k to round_up(p, 32), padding zero
+  float* Hp;     // rpy rows, k to round_up(n, 32), padded rows and columns zero
   float* GH;     // rp x rp
   float* GW;     // rp x rp
   float* gpart;  // max(tilesW, tilesH) x rp x rp partial Grams
   float* W;      // caller's W (p x r)
   float* H;      // caller's H (r x n)
-  int64_t ldv, ldvt, ldsrc, ldh, ldwt;
+  int64_t ldv, ldvt, ldsrc, ldh, ldwt;  // row pitches (floats), see spread()
   int32_t p, n, r, rp;  // rp = r rounded up to 16; rpy = rp rounded up to 32
   int32_t msw, msh;     // phase W tile rows = 64 msw; phase H tile columns = 64 msh
   int32_t tilesW, tilesH;
@@ -865,6 +865,11 @@ __global__ void k_batch_fill(uint32_t* __restrict__ p, int64_t count) {
 // ---------------------------------------------------------------------------
 inline int64_t up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Row pitch (floats) of a streamed matrix: 64 floats (256 bytes) more when
+// the pitch is a multiple of 4 KB, so that the rows of one copy-ring stage
+// spread over the HBM channels (as for the single-problem copies).
+inline int64_t spread(int64_t elems) { return (elems * 4) % 4096 == 0 ? elems + 64 : elems; }
+
 }  // namespace
 }  // namespace nmfb
 
@@ -1118,7 +1123,7 @@ nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t c
     oW[i] = off;
     off += up(q.p * rp * 4, 256);
     oH[i] = off;
-    off += up(rpy_of(rp) * up(q.n, 32) * 4, 256);
+    off += up(rpy_of(rp) * spread(up(q.n, 32)) * 4, 256);
   }
   for (int i = 0; i < count; ++i) {
     const int64_t rp = up(probs[i].r, 16);
@@ -1136,14 +1141,14 @@ nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t c
     oP[i] = off;
     off += up(tiles * rp * rp * 4, 256);
     oWT[i] = off;
-    off += up(rpy_of(rp) * up(q.p, 32) * 4, 256);
+    off += up(rpy_of(rp) * spread(up(q.p, 32)) * 4, 256);
   }
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = probs[i];
     oV[i] = off;
-    off += up(up(q.p, 128) * up(q.n, 32) * 4, 1024);
+    off += up(up(q.p, 128) * spread(up(q.n, 32)) * 4, 1024);
     oVT[i] = off;
-    off += up(up(q.n, 128) * up(q.p, 32) * 4, 1024);
+    off += up(up(q.n, 128) * spread(up(q.p, 32)) * 4, 1024);
   }
   if (hipMalloc(&b->arena, off) != hipSuccess) return fail(NMF_ENOMEM);
   if (hipMemsetAsync(b->arena, 0, off, b->st) != hipSuccess) return fail(NMF_EDEVICE);
@@ -1153,17 +1158,17 @@ nmf_status nmf_batch_create(nmf_batch** out, const nmf_problem* probs, int32_t c
     P.Vsrc = q.V;
     P.ldsrc = q.ldv;
     P.V = reinterpret_cast<float*>(b->arena + oV[i]);
-    P.ldv = up(q.n, 32);
+    P.ldv = spread(up(q.n, 32));
     P.VT = reinterpret_cast<float*>(b->arena + oVT[i]);
-    P.ldvt = up(q.p, 32);
+    P.ldvt = spread(up(q.p, 32));
     P.p = (int32_t)q.p;
     P.n = (int32_t)q.n;
     P.r = q.r;
     P.rp = (int32_t)up(q.r, 16);
-    P.ldh = up(q.n, 32);
-    P.ldwt = up(q.p, 32);
-    P.kw = (int32_t)(P.ldv / 32);
-    P.kh = (int32_t)(P.ldvt / 32);
+    P.ldh = spread(up(q.n, 32));
+    P.ldwt = spread(up(q.p, 32));
+    P.kw = (int32_t)(up(q.n, 32) / 32);
+    P.kh = (int32_t)(up(q.p, 32) / 32);
     P.Wp = reinterpret_cast<float*>(b->arena + oW[i]);
     P.Hp = reinterpret_cast<float*>(b->arena + oH[i]);
     P.WT = reinterpret_cast<float*>(b->arena + oWT[i]);

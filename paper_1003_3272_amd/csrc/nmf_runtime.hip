@@ -8,9 +8,12 @@
 //                 -> G_H = H H^T                     (for the next W half-step)
 //
 // Internal layout (row-major, zero padded; ppad = round_up(p, 256),
-// npad = round_up(n, 256), rp = padded rank):
+// npad = round_up(n, 256), rp = padded rank; the streamed copies get row
+// pitches from spread_pitch, i.e. npad / ppad plus 128 bytes when that is a
+// multiple of 4 KB):
 //   Wp (ppad x rp), Hp (rp x npad), G_H and G_W (rp x rp)
-//   FP32:  V itself when p, n are multiples of 256 (else a ppad x npad copy),
+//   FP32:  V itself when p, n are multiples of 256 and its pitch is not a
+//          multiple of 4 KB (else a padded ppad x npad copy),
 //          VT = V^T (npad x ppad), WT = W^T (rp x ppad)
 //   BF16:  Vb = bf16(V) (ppad x npad), VTb = bf16(V^T) (npad x ppad),
 //          Hb = bf16(H) (rp x npad), WbT = bf16(W^T) (rp x ppad)
@@ -38,6 +41,16 @@ constexpr int64_t kMaxDim = 4000000;  // objective grid.y = ceil(p / 64) <= 6553
 constexpr int32_t kGraphChunk = 16;    // iterations per replay of the large graph
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Row pitch for a matrix streamed through the copy ring: a pitch that is a
+// multiple of 4 KB puts the 100+ rows of one ring stage on the same few HBM
+// channels, so such pitches get pad_bytes more.  Measured at 4096 x 16384,
+// rank 16, FP32 (pass 1 on V, pass 2 on V^T, microseconds per launch):
+// pad 0: 84 / 69; 128 B: 52 / 74; 256 B: 53 / 50; 512 B: 80 / 50;
+// 1 KB: 53 / 50.  The BF16 copies are insensitive (128 B is marginally best).
+inline int64_t spread_pitch(int64_t elems, int esize, int64_t pad_bytes) {
+  return (elems * esize) % 4096 == 0 ? elems + pad_bytes / esize : elems;
+}
 
 int64_t env_int(const char* name, int64_t dflt) {
   const char* v = std::getenv(name);
@@ -90,6 +103,9 @@ struct nmf_ctx {
   const float* Vk = nullptr;  // V as read by the kernels
   int64_t ldvk = 0;
   int64_t ppad = 0, npad = 0;
+  // row pitches (elements) of the streamed copies: bf16(V), V^T / bf16(V^T)
+  // and W^T / bf16(W^T); see spread_pitch
+  int64_t lvb = 0, lvt = 0, lwt = 0;
 
   // workspace (one allocation, carved)
   void* ws = nullptr;
@@ -204,7 +220,7 @@ nmf_status gram_h(nmf_ctx* c) {
 nmf_status gram_w(nmf_ctx* c) {
   StageTimer t(c, NMF_STAGE_GRAM_W);
   if (c->bf16) {
-    TRY_HIP(launch_gemm_nt_bf16(c->cgh, c->WbT, c->ppad, c->rp, c->WbT, c->ppad, c->rp, c->p,
+    TRY_HIP(launch_gemm_nt_bf16(c->cgh, c->WbT, c->lwt, c->rp, c->WbT, c->lwt, c->rp, c->p,
                                 c->sgw.splits, c->sgw.kchunk, c->partg, c->sgw.ldp, c->sgw.sp,
                                 kNoGram, c->st));
   } else {
@@ -223,7 +239,7 @@ nmf_status half_w(nmf_ctx* c) {
     StageTimer t(c, NMF_STAGE_GEMM_VHT);
     const void* X = c->bf16 ? static_cast<const void*>(c->Vb) : static_cast<const void*>(c->Vk);
     const void* Y = c->bf16 ? static_cast<const void*>(c->Hb) : static_cast<const void*>(c->Hp);
-    TRY_HIP(launch_nt_dma(c->d1, c->bf16, X, c->bf16 ? c->npad : c->ldvk, c->p, Y, c->npad,
+    TRY_HIP(launch_nt_dma(c->d1, c->bf16, X, c->bf16 ? c->lvb : c->ldvk, c->p, Y, c->npad,
                           c->rp, c->npad, c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp,
                           c->s1.sp, gr, c->st));
   }
@@ -231,7 +247,7 @@ nmf_status half_w(nmf_ctx* c) {
     StageTimer t(c, NMF_STAGE_UPDATE_W);
     TRY_HIP(launch_update_w(c->rp, c->p, c->r, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits,
                             c->GH, c->Wp, c->Wuser, c->bf16 ? nullptr : c->WT,
-                            c->bf16 ? c->WbT : nullptr, c->ppad, c->bf16,
+                            c->bf16 ? c->WbT : nullptr, c->lwt, c->bf16,
                             c->fuse ? c->gpw : nullptr, c->uw_grid, false, c->st));
   }
   return c->fuse ? NMF_OK : gram_w(c);
@@ -243,7 +259,7 @@ nmf_status half_h(nmf_ctx* c) {
     StageTimer t(c, NMF_STAGE_GEMM_WTV);
     const void* X = c->bf16 ? static_cast<const void*>(c->WbT) : static_cast<const void*>(c->WT);
     const void* Y = c->bf16 ? static_cast<const void*>(c->VTb) : static_cast<const void*>(c->VT);
-    TRY_HIP(launch_nt_dma(c->d2, c->bf16, X, c->ppad, c->rp, Y, c->ppad, c->n, c->ppad,
+    TRY_HIP(launch_nt_dma(c->d2, c->bf16, X, c->lwt, c->rp, Y, c->lvt, c->n, c->ppad,
                           c->s2.splits, c->s2.kchunk, c->part2, c->s2.ldp, c->s2.sp, gr, c->st));
   }
   {
@@ -323,8 +339,19 @@ nmf_status setup(nmf_ctx* c) {
   // rows in the BF16 tier, whose products read the bf16 shadows) a
   // zero-padded ppad x npad copy.
   const bool aligned = (reinterpret_cast<uintptr_t>(c->Vuser) % 16 == 0) && (c->ldv % 4 == 0);
-  const bool need_copy = !aligned || (!c->bf16 && (p % 256 != 0 || n % 256 != 0));
-  c->ldvk = need_copy ? npad : c->ldv;
+  const bool bad_pitch = (c->ldv * 4) % 4096 == 0;
+  const bool need_copy =
+      !aligned || (!c->bf16 && (p % 256 != 0 || n % 256 != 0 || bad_pitch));
+  // pad of a pitch that is a multiple of 4 KB, per copy (bytes, multiples of
+  // 128; NMF_PAD_V / _VB / _VT override them)
+  const int64_t pad_v = env_int("NMF_PAD_V", 256) / 128 * 128;
+  const int64_t pad_vb = env_int("NMF_PAD_VB", 128) / 128 * 128;
+  const int64_t pad_vt = env_int("NMF_PAD_VT", c->bf16 ? 128 : 256) / 128 * 128;
+  c->ldvk = need_copy ? spread_pitch(npad, 4, pad_v) : c->ldv;
+  const int es = c->bf16 ? 2 : 4;
+  c->lvb = spread_pitch(npad, 2, pad_vb);
+  c->lvt = spread_pitch(ppad, es, pad_vt);
+  c->lwt = spread_pitch(ppad, es, pad_vt);
 
   // tiles and splits (environment overrides are tuning knobs)
   const int64_t target = env_int("NMF_SPLIT_TARGET", 512);
@@ -362,7 +389,7 @@ nmf_status setup(nmf_ctx* c) {
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  const size_t oVc = need_copy ? take(sizeof(float) * (size_t)ppad * npad) : 0;
+  const size_t oVc = need_copy ? take(sizeof(float) * (size_t)ppad * c->ldvk) : 0;
   const size_t oWp = take(sizeof(float) * (size_t)ppad * rp);
   const size_t oHp = take(sizeof(float) * (size_t)rp * npad);
   const size_t oGH = take(sizeof(float) * (size_t)rp * rp);
@@ -380,13 +407,13 @@ nmf_status setup(nmf_ctx* c) {
   const size_t oli = c->fuse ? take(sizeof(double) * (size_t)rp * rp) : 0;
   size_t oVT = 0, oWT = 0, oVb = 0, oVTb = 0, oHb = 0, oWbT = 0;
   if (!c->bf16) {
-    oVT = take(sizeof(float) * (size_t)npad * ppad);
-    oWT = take(sizeof(float) * (size_t)rp * ppad);
+    oVT = take(sizeof(float) * (size_t)npad * c->lvt);
+    oWT = take(sizeof(float) * (size_t)rp * c->lwt);
   } else {
-    oVb = take(sizeof(uint16_t) * (size_t)ppad * npad);
-    oVTb = take(sizeof(uint16_t) * (size_t)npad * ppad);
+    oVb = take(sizeof(uint16_t) * (size_t)ppad * c->lvb);
+    oVTb = take(sizeof(uint16_t) * (size_t)npad * c->lvt);
     oHb = take(sizeof(uint16_t) * (size_t)rp * npad);
-    oWbT = take(sizeof(uint16_t) * (size_t)rp * ppad);
+    oWbT = take(sizeof(uint16_t) * (size_t)rp * c->lwt);
   }
   if (hipMalloc(&c->ws, off) != hipSuccess) {
     c->ws = nullptr;
@@ -452,13 +479,13 @@ nmf_status setup(nmf_ctx* c) {
   TRY_HIP(launch_copy_pad(c->Huser, n, c->r, n, c->Hp, npad, c->st));
 
   if (!c->bf16) {
-    TRY_HIP(launch_transpose_f32(c->Vk, c->ldvk, p, n, c->VT, ppad, c->st));
-    TRY_HIP(launch_transpose_f32(c->Wp, rp, ppad, rp, c->WT, ppad, c->st));
+    TRY_HIP(launch_transpose_f32(c->Vk, c->ldvk, p, n, c->VT, c->lvt, c->st));
+    TRY_HIP(launch_transpose_f32(c->Wp, rp, ppad, rp, c->WT, c->lwt, c->st));
   } else {
-    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->Vb, npad, false, c->st));
-    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->VTb, ppad, true, c->st));
+    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->Vb, c->lvb, false, c->st));
+    TRY_HIP(launch_cast_bf16(c->Vk, c->ldvk, p, n, c->VTb, c->lvt, true, c->st));
     TRY_HIP(launch_cast_bf16(c->Hp, npad, rp, npad, c->Hb, npad, false, c->st));
-    TRY_HIP(launch_cast_bf16(c->Wp, rp, ppad, rp, c->WbT, ppad, true, c->st));
+    TRY_HIP(launch_cast_bf16(c->Wp, rp, ppad, rp, c->WbT, c->lwt, true, c->st));
   }
 
   // ||V||_F^2 (objective with W = 0), then the Grams of the start
@@ -618,7 +645,7 @@ nmf_status nmf_refit_w(nmf_ctx* c, float floor_rel) {
   const GramRed gr = GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH};
   const void* X = c->bf16 ? static_cast<const void*>(c->Vb) : static_cast<const void*>(c->Vk);
   const void* Y = c->bf16 ? static_cast<const void*>(c->Hb) : static_cast<const void*>(c->Hp);
-  TRY_HIP(launch_nt_dma(c->d1, c->bf16, X, c->bf16 ? c->npad : c->ldvk, c->p, Y, c->npad, c->rp,
+  TRY_HIP(launch_nt_dma(c->d1, c->bf16, X, c->bf16 ? c->lvb : c->ldvk, c->p, Y, c->npad, c->rp,
                         c->npad, c->s1.splits, c->s1.kchunk, c->part1, c->s1.ldp, c->s1.sp, gr,
                         c->st));
   TRY_HIP(launch_ls_refit(c->GH, c->rp, c->r, c->p, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits,
