@@ -13,7 +13,8 @@ Prints one JSON line: iterations/s, the roofline of the dominant kernel
 (from HIP events recorded around every stage inside the timed region) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
 
-Then (unless --no-batch) the batched tier: 512 problems of uneven shape,
+Then (unless --no-precision-tier) the FP32 and BF16 tiers at 8192 x 32768
+for ranks 32, 128 and 256, then (unless --no-batch) the batched tier: 512 problems of uneven shape,
 200 iterations each in one persistent launch, against a loop of the
 single-problem solver.  Then (unless --no-warm-start) the time-to-tolerance
 experiment: a stream of
@@ -51,6 +52,10 @@ def parse():
     ap.add_argument("--ldv-pad", type=int, default=0,
                     help="extra floats per V row in device memory (row-stride experiment)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-tier run")
+    ap.add_argument("--no-precision-tier", action="store_true",
+                    help="skip the 8192 x 32768 FP32 / BF16 rank sweep")
+    ap.add_argument("--pt-iters", type=int, default=200)
+    ap.add_argument("--pt-ranks", type=int, nargs="+", default=[32, 128, 256])
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first copy 256 MiB between two device buffers (a plain copy kernel "
                          "of known size, the reference for hardware byte counters)")
@@ -117,6 +122,70 @@ def measured_traffic(stage, p, n, r, precision):
     if not sha or not val or h.hexdigest() != sha.group(1):
         return None
     return int(val.group(1))
+
+
+def _precision_case(r):
+    from synth import generators as gen
+    return gen.precision_tier(r)
+
+
+def precision_tier_experiment(args, log):
+    """8192 x 32768, planted rank r in {32, 128, 256}: iterations/s of the
+    FP32 and BF16 tiers over 200 iterations from the same start, each pass's
+    roofline, and the BF16 objective relative to FP32 (which matches the
+    float64 oracle to 1e-5 by the parity tests)."""
+    import numpy as np
+    import torch
+
+    from paper_1003_3272_amd import nmf
+
+    out = {"workload": "8192x32768 image-like V (Gamma(2,0.5) x sparse Exp, rescaled), seed "
+                       "1003+r, U(0,1) start seed 2003+r", "iterations": args.pt_iters, "ranks": {}}
+    for r in args.pt_ranks:
+        t0 = time.perf_counter()
+        V, W0, H0 = _precision_case(r)
+        t_gen = time.perf_counter() - t0
+        Vd = torch.from_numpy(V).cuda()
+        del V
+        res = {"generate_s": round(t_gen, 1)}
+        for prec in ("fp32", "bf16"):
+            Wd, Hd = torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda()
+            with nmf.Nmf(Vd, Wd, Hd, precision=prec) as ctx:
+                ctx.step(2)
+                torch.cuda.synchronize()
+                ctx.profile_start(8 * args.pt_iters)
+                t0 = time.perf_counter()
+                ctx.step(args.pt_iters - 2)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                st = ctx.profile_stop()
+                f = ctx.objective()
+                nv2 = ctx.data_norm2()
+            p_, n_ = Vd.shape
+            passes = {k: st[k][0] / max(1, st[k][1]) for k in ("gemm_vht", "gemm_wtv")}
+            dom = max(passes, key=passes.get)
+            flops = 2.0 * p_ * n_ * r
+            vbytes = p_ * n_ * (4 if prec == "fp32" else 2)
+            tf = flops / (passes[dom] * 1e-3) / 1e12
+            gbs = vbytes / (passes[dom] * 1e-3) / 1e9
+            if flops / (PEAK_TFLOPS[prec] * 1e12) >= vbytes / (PEAK_HBM_GBS * 1e9):
+                roof = {"bound": "mfma", "frac": round(tf / PEAK_TFLOPS[prec], 4)}
+            else:
+                roof = {"bound": "hbm", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+            res[prec] = {"iters_per_s": round((args.pt_iters - 2) / el, 1),
+                         "pass_ms": round(passes[dom], 4), "tflops": round(tf, 1),
+                         "v_pass_gbs": round(gbs, 1), "roofline": roof,
+                         "objective": f, "gap": f / nv2}
+            del Wd, Hd
+        res["bf16_rel_objective_vs_fp32"] = abs(res["bf16"]["objective"] - res["fp32"]["objective"]) \
+            / res["fp32"]["objective"]
+        res["bf16_speedup"] = round(res["bf16"]["iters_per_s"] / res["fp32"]["iters_per_s"], 2)
+        out["ranks"][str(r)] = res
+        log(f"precision tier r={r}: fp32 {res['fp32']['iters_per_s']} it/s, bf16 "
+            f"{res['bf16']['iters_per_s']} it/s, rel f {res['bf16_rel_objective_vs_fp32']:.2e}")
+        del Vd
+        torch.cuda.empty_cache()
+    return out
 
 
 def _gen_batch_problem(args):
@@ -381,6 +450,10 @@ def main():
     }
     del Vd, Wd, Hd
     torch.cuda.empty_cache()
+    if not args.no_precision_tier:
+        out["precision_tier"] = precision_tier_experiment(
+            args, lambda msg: print(msg, file=sys.stderr, flush=True))
+        torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = batched_experiment(
             args, lambda msg: print(msg, file=sys.stderr, flush=True))
