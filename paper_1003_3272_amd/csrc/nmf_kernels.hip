@@ -651,28 +651,29 @@ __global__ void k_reduce_gram(const float* __restrict__ part, int64_t ldp,
 // A workgroup takes ROWS rows of W at a time (grid-stride) with all RP
 // ranks; it snapshots the rows in LDS (rounded to bf16 in the BF16 tier,
 // where the product takes bf16 operands) and streams G through LDS in chunks
-// of KC columns.  Each thread produces 4 adjacent ranks of one row per chunk
-// (ROWS * KC / 4 == 256).
+// of KC columns.  Each thread produces KPT adjacent ranks of one row per
+// chunk (ROWS * KC / KPT == 256): KPT = 4, or 1 when p is too small for the
+// 4-rank blocks to number 256.  Both forms add in the same order.
 // With gout != nullptr (RP <= 64) the workgroup also accumulates the Gram
 // W_new^T W_new of the rows it updated (bf16-rounded in the BF16 tier) and
 // writes it to gout[blockIdx.x]; the next product kernel reduces these.
 // gram_only skips the update and only forms the Gram of the current W.
 // ---------------------------------------------------------------------------
-template <int RP>
+template <int RP, int KPT>
 __global__ __launch_bounds__(256) void k_update_w(
     int64_t p, int r, const float* __restrict__ part, int64_t ldp, int64_t sp,
     int splits, const float* __restrict__ G, float* __restrict__ Wp,
     float* __restrict__ Wc, float* __restrict__ WT, uint16_t* __restrict__ WbT, int64_t ldwt,
     int bf16, float* __restrict__ gout, int gram_only) {
   constexpr int KC = RP < 64 ? RP : 64;
-  constexpr int ROWS = 1024 / KC;
+  constexpr int ROWS = 256 * KPT / KC;    // KPT rank entries per thread (4, or 1 for small p)
   constexpr bool FUSE = RP <= 64;         // Gram partial fits one thread tile
   constexpr int TB = RP / 16;             // Gram tile per thread: TB x TB
   __shared__ __attribute__((aligned(16))) float Ws[ROWS * RP];
   __shared__ __attribute__((aligned(16))) float Gs[RP * KC];
   __shared__ __attribute__((aligned(16))) float Wn[FUSE ? ROWS * RP : 4];
   const int tid = threadIdx.x;
-  const int i = tid / (KC / 4), k4 = 4 * (tid % (KC / 4));
+  const int i = tid / (KC / KPT), k4 = KPT * (tid % (KC / KPT));
   const bool gram = FUSE && gout != nullptr;
   const int gk = (tid / 16) * TB, gl = (tid % 16) * TB;
   float ga[TB][TB];
@@ -710,6 +711,32 @@ __global__ __launch_bounds__(256) void k_update_w(
         }
         __syncthreads();
         const int k = kc0 + k4;
+        if constexpr (KPT == 1) {
+          float wn = 0.f;
+          if (row < p) {
+            float a = 0.f;
+            int q = 0;
+            for (; q + 8 <= splits; q += 8) {
+              float v[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) v[u] = part[(q + u) * sp + row * ldp + k];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) a += v[u];
+            }
+            for (; q < splits; ++q) a += part[q * sp + row * ldp + k];
+            float b = 0.f;
+#pragma unroll 8
+            for (int l = 0; l < RP; ++l) b = fmaf(Ws[i * RP + l], Gs[l * KC + k4], b);
+            const float w = Wp[row * RP + k];
+            wn = (b > 0.f) ? w * (a / b) : w;
+            Wp[row * RP + k] = wn;
+            if (k < r) Wc[row * r + k] = wn;
+            if (WT) WT[(int64_t)k * ldwt + row] = wn;
+            if (WbT) WbT[(int64_t)k * ldwt + row] = to_bf16(wn);
+          }
+          if (FUSE) Wn[i * RP + k] = bf16 ? bf16_val(wn) : wn;
+          continue;
+        }
         float4 wn = make_float4(0.f, 0.f, 0.f, 0.f);
         if (row < p) {
           const float4 a = sum_splits4(part, row * ldp + k, sp, splits);
@@ -776,18 +803,19 @@ __global__ __launch_bounds__(256) void k_update_w(
 //   s_kj = sum_s part[s][k][j]                 (numerator (W^T V)_kj)
 //   d_kj = sum_l G_kl h_lj                     (denominator ((W^T W) H)_kj)
 //   h_kj <- h_kj * (s_kj / d_kj)  if d_kj > 0, else unchanged.
-// A workgroup takes COLS = 64 columns of H at a time (grid-stride) with all
-// RP ranks; each thread produces 4 adjacent columns of one rank at a time.
+// A workgroup takes COLS columns of H at a time (grid-stride) with all RP
+// ranks: 64, or 32 / 16 when n is too small for 64-column blocks to number
+// 256; each thread produces 4 adjacent columns of one rank at a time.
 // With gout != nullptr (RP <= 64) it also accumulates the Gram H_new H_new^T
 // of its columns into gout[blockIdx.x]; gram_only skips the update.
 // ---------------------------------------------------------------------------
-template <int RP>
+template <int RP, int COLS>
 __global__ __launch_bounds__(256) void k_update_h(
     int64_t n, int r, const float* __restrict__ part, int64_t ldp, int64_t sp,
     int splits, const float* __restrict__ G, float* __restrict__ Hp,
     int64_t ldh, float* __restrict__ Hc, uint16_t* __restrict__ Hb, int bf16,
     float* __restrict__ gout, int gram_only) {
-  constexpr int COLS = 64, KC = RP < 64 ? RP : 64;
+  constexpr int KC = RP < 64 ? RP : 64;
   constexpr bool FUSE = RP <= 64;
   constexpr int TB = RP / 16;
   __shared__ __attribute__((aligned(16))) float Hs[RP * COLS];
@@ -1531,15 +1559,31 @@ hipError_t launch_reduce_gram(const float* part, int64_t ldp, int64_t sp, int sp
     default: return hipErrorInvalidValue; \
   }
 
+// Rank entries per thread of k_update_w: 4 (1024 / KC rows per block), or 1
+// (a quarter of the rows per block) when 4 would leave fewer than 256 blocks.
+int update_w_kpt(int rp, int64_t p) {
+  const int64_t per4 = 1024 / (rp < 64 ? rp : 64);
+  return (p + per4 - 1) / per4 >= 256 ? 4 : 1;
+}
+
 int update_grid(int rp, int64_t extent, int cap) {
-  const int64_t per = 1024 / (rp < 64 ? rp : 64);  // rows per block of k_update_w
+  const int64_t per = update_w_kpt(rp, extent) * 256 / (rp < 64 ? rp : 64);  // rows per block
   int64_t blocks = (extent + per - 1) / per;
   if (cap > 0 && blocks > cap) blocks = cap;
   return (int)(blocks < 1 ? 1 : blocks);
 }
 
+// Columns per block of k_update_h: 64, or 32 / 16 when that leaves fewer
+// than 256 blocks (a small problem would otherwise occupy few CUs).
+int update_h_cols(int64_t n) {
+  if ((n + 63) / 64 >= 256) return 64;
+  if ((n + 31) / 32 >= 256) return 32;
+  return 16;
+}
+
 int update_h_grid(int64_t n, int cap) {
-  int64_t blocks = (n + 63) / 64;
+  const int cols = update_h_cols(n);
+  int64_t blocks = (n + cols - 1) / cols;
   if (cap > 0 && blocks > cap) blocks = cap;
   return (int)(blocks < 1 ? 1 : blocks);
 }
@@ -1549,8 +1593,14 @@ hipError_t launch_update_w(int rp, int64_t p, int r, const float* part, int64_t 
                            uint16_t* WbT, int64_t ldwt, bool bf16, float* gout, int grid,
                            bool gram_only, hipStream_t st) {
 #define UW(R)                                                                                  \
-  hipLaunchKernelGGL(k_update_w<R>, dim3(grid), dim3(256), 0, st, p, r, part, ldp, sp, splits, G, \
-                     Wp, Wcaller, WT, WbT, ldwt, (int)bf16, gout, (int)gram_only)
+  do {                                                                                          \
+    if (update_w_kpt(R, p) == 4)                                                                \
+      hipLaunchKernelGGL((k_update_w<R, 4>), dim3(grid), dim3(256), 0, st, p, r, part, ldp, sp,   \
+                         splits, G, Wp, Wcaller, WT, WbT, ldwt, (int)bf16, gout, (int)gram_only); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_update_w<R, 1>), dim3(grid), dim3(256), 0, st, p, r, part, ldp, sp,   \
+                         splits, G, Wp, Wcaller, WT, WbT, ldwt, (int)bf16, gout, (int)gram_only); \
+  } while (0)
   RP_SWITCH(rp, UW)
 #undef UW
   return hipGetLastError();
@@ -1561,8 +1611,18 @@ hipError_t launch_update_h(int rp, int64_t n, int r, const float* part, int64_t 
                            uint16_t* Hb, bool bf16, float* gout, int grid, bool gram_only,
                            hipStream_t st) {
 #define UH(R)                                                                                  \
-  hipLaunchKernelGGL(k_update_h<R>, dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, splits, G, \
-                     Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only)
+  do {                                                                                          \
+    const int cols = update_h_cols(n);                                                          \
+    if (cols == 64)                                                                             \
+      hipLaunchKernelGGL((k_update_h<R, 64>), dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, \
+                         splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only);     \
+    else if (cols == 32)                                                                        \
+      hipLaunchKernelGGL((k_update_h<R, 32>), dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, \
+                         splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only);     \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_update_h<R, 16>), dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, \
+                         splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only);     \
+  } while (0)
   RP_SWITCH(rp, UH)
 #undef UH
   return hipGetLastError();
