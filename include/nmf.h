@@ -126,12 +126,16 @@ nmf_status nmf_objective(nmf_ctx* ctx, double* f_host);
 
 /* Iterate until the stopping rule of the context's options holds or
    max_iters iterations have run.  The objective is evaluated at the start
-   and after every check_every iterations (and after the last one).
-   *iters_done_host receives the number of iterations run and *f_host the
-   last objective.  trace_host (may be NULL) receives the evaluated
-   objectives, f_0 first, up to trace_len entries.  Returns NMF_OK when the
-   rule held, NMF_ENOTCONVERGED at the cap, NMF_ENONFINITE if f became
-   non-finite. */
+   and after every check_every iterations (and after the last one).  The
+   next chunk of iterations and its check are enqueued before the host
+   reads the current check, so the device does not wait on the host: when
+   the rule holds at a check, the chunk already enqueued after it (if any)
+   also runs, so up to check_every iterations more than the first passing
+   check.  *iters_done_host receives the number of iterations run and
+   *f_host the objective of the factors left in W and H (the last check).
+   trace_host (may be NULL) receives the evaluated objectives, f_0 first,
+   up to trace_len entries.  Returns NMF_OK when the rule held at a check,
+   NMF_ENOTCONVERGED at the cap, NMF_ENONFINITE if f became non-finite. */
 nmf_status nmf_solve(nmf_ctx* ctx, int32_t max_iters, int32_t* iters_done_host,
                      double* f_host, double* trace_host, int32_t trace_len);
 

@@ -78,7 +78,9 @@ struct DmaCfg {
   int bm, bn;
   int threads;
 };
-DmaCfg dma_config(int rp, bool pass1);
+// Tile of the V-streaming products for padded rank rp; narrow: the 64-wide
+// tiles for problems whose default tiling leaves fewer than 256 workgroups.
+DmaCfg dma_config(int rp, bool pass1, bool narrow = false);
 DmaCfg dma_config_by_id(int id);
 hipError_t launch_nt_dma(const DmaCfg& cfg, bool bf16, const void* X, int64_t ldx,
                          int64_t M, const void* Y, int64_t ldy, int64_t N, int64_t K,
@@ -98,9 +100,14 @@ hipError_t launch_reduce_gram(const float* part, int64_t ldp, int64_t sp,
                               int splits, int rp, float* G, uint16_t* Gbf,
                               hipStream_t st);
 
+// Block shapes of the update kernels: rank entries per thread of the W
+// update (4 or 1) and columns per block of the H update (64, 32 or 16),
+// narrowed when the full shape would leave fewer than 256 workgroups.
+int update_w_kpt(int rp, int64_t p);
+int update_h_cols(int64_t n);
 // Number of workgroups of the update kernels (grid-stride; capped at cap).
-int update_grid(int rp, int64_t p, int cap);
-int update_h_grid(int64_t n, int cap);
+int update_grid(int rp, int64_t p, int cap, int kpt);
+int update_h_grid(int64_t n, int cap, int cols);
 
 // W half-step epilogue.  Wp (ppad x rp) holds the current W; A partials are
 // part[s][i][k] (pitch ldp, split pitch sp).  Writes the new W to Wp, to the
@@ -112,7 +119,7 @@ hipError_t launch_update_w(int rp, int64_t p, int r, const float* part,
                            int64_t ldp, int64_t sp, int splits, const float* G,
                            float* Wp, float* Wcaller, float* WT, uint16_t* WbT,
                            int64_t ldwt, bool bf16, float* gout, int grid,
-                           bool gram_only, hipStream_t st);
+                           int kpt, bool gram_only, hipStream_t st);
 
 // H half-step epilogue.  Hp (rp x ldh) holds the current H; S partials are
 // part[s][k][j].  Writes Hp, the caller's H (r x n) and, for the BF16 tier,
@@ -120,8 +127,8 @@ hipError_t launch_update_w(int rp, int64_t p, int r, const float* part,
 hipError_t launch_update_h(int rp, int64_t n, int r, const float* part,
                            int64_t ldp, int64_t sp, int splits, const float* G,
                            float* Hp, int64_t ldh, float* Hcaller, uint16_t* Hb,
-                           bool bf16, float* gout, int grid, bool gram_only,
-                           hipStream_t st);
+                           bool bf16, float* gout, int grid, int cols,
+                           bool gram_only, hipStream_t st);
 
 // Objective partials: one double per 64 x 64 tile of V - W H.
 hipError_t launch_objective(int rp, const float* V, int64_t ldv, int64_t p,

@@ -577,6 +577,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
   // st - 1, whose buffer is then refilled with stage st + S - 1.
   const int pre = nst < S - 1 ? nst : S - 1;
   for (int st = 0; st < pre; ++st) issue(st);
+  // Gram of the previous update, reduced here (under the latency of the
+  // first copies) so the next kernel can use it.  Its loads and stores only
+  // make the ring's vmcnt waits below stricter.
+  gram_reduce_slice(gr);
   for (int st = 0; st < nst; ++st) {
     const int later = nst - 1 - st;
     wait_stage<L, S>(later < S - 2 ? later : S - 2);
@@ -584,8 +588,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
     if (st + S - 1 < nst) issue(st + S - 1);
     compute(lds + (st % S) * STAGE);
   }
-  // Gram of the previous update, reduced here so the next kernel can use it
-  gram_reduce_slice(gr);
 
   float* P = part + (int64_t)blockIdx.x * sp;
 #pragma unroll
@@ -623,6 +625,38 @@ __device__ __forceinline__ float4 sum_splits4(const float* __restrict__ part, in
     s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
   }
   return s;
+}
+
+__device__ __forceinline__ void add4(float4& s, const float4& v) {
+  s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+}
+__device__ __forceinline__ void add4(float& s, float v) { s += v; }
+
+// Split-K sums of NI items at once (each a float4 or a float at part + off,
+// split pitch sp), every item summed in ascending split order.  The loads
+// of B splits of all NI items are issued before any of them is added, so a
+// tile's items cost one memory round trip per B splits.
+template <int NI, int B, typename T>
+__device__ __forceinline__ void sum_splits_batch(const float* __restrict__ part,
+                                                 const int64_t (&off)[NI], const bool (&ok)[NI],
+                                                 int64_t sp, int splits, T (&s)[NI]) {
+#pragma unroll
+  for (int e = 0; e < NI; ++e) s[e] = T{};
+  for (int q = 0; q < splits; q += B) {
+    T v[NI][B];
+#pragma unroll
+    for (int e = 0; e < NI; ++e)
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        v[e][u] = T{};
+        if (ok[e] && q + u < splits) v[e][u] = *reinterpret_cast<const T*>(part + (q + u) * sp + off[e]);
+      }
+#pragma unroll
+    for (int e = 0; e < NI; ++e)
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (q + u < splits) add4(s[e], v[e][u]);
+  }
 }
 
 // Gram reduction: G[m][c] = sum_s part[s][m][c], s ascending; 4 columns per
@@ -685,6 +719,104 @@ __global__ __launch_bounds__(256) void k_update_w(
   for (int64_t blk = blockIdx.x; blk * ROWS < p; blk += gridDim.x) {
     const int64_t i0 = blk * ROWS;
     const int64_t row = i0 + i;
+    if (FUSE && !gram_only) {
+      // All global loads of the row block are issued before the first wait:
+      // the rows (one float4 per thread), this thread's split sums and, on
+      // the first block, G.  KC == RP here, and for KPT == 4 the float4 a
+      // thread loads is the one it updates.
+      constexpr int NQ = ROWS * RP / 4;
+      constexpr int NG = (RP * RP / 4 + 255) / 256;
+      const bool tq = NQ % 256 == 0 || tid < NQ;
+      const int ti = tid / (RP / 4), tl4 = 4 * (tid % (RP / 4));
+      const bool first = blk == blockIdx.x;
+      float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (tq && i0 + ti < p) wt = *reinterpret_cast<const float4*>(&Wp[(i0 + ti) * RP + tl4]);
+      float4 gq[NG];
+#pragma unroll
+      for (int e = 0; e < NG; ++e) {
+        const int idx = tid + 256 * e;
+        gq[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (first && idx < RP * RP / 4) gq[e] = *reinterpret_cast<const float4*>(&G[4 * idx]);
+      }
+      const int64_t off[1] = {row * ldp + k4};
+      const bool ok[1] = {row < p};
+      float4 a4[1];
+      float a1[1];
+      float w1 = 0.f;
+      if constexpr (KPT == 4) {
+        sum_splits_batch<1, 16>(part, off, ok, sp, splits, a4);
+      } else {
+        if (row < p) w1 = Wp[row * RP + k4];
+        sum_splits_batch<1, 16>(part, off, ok, sp, splits, a1);
+      }
+      __syncthreads();
+      if (tq) {
+        float4 w = wt;
+        if (bf16) {
+          w.x = bf16_val(w.x); w.y = bf16_val(w.y); w.z = bf16_val(w.z); w.w = bf16_val(w.w);
+        }
+        *reinterpret_cast<float4*>(&Ws[ti * RP + tl4]) = w;
+      }
+      if (first) {
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+          const int idx = tid + 256 * e;
+          float4 gv = gq[e];
+          if (bf16) {
+            gv.x = bf16_val(gv.x); gv.y = bf16_val(gv.y); gv.z = bf16_val(gv.z); gv.w = bf16_val(gv.w);
+          }
+          if (idx < RP * RP / 4) *reinterpret_cast<float4*>(&Gs[4 * idx]) = gv;
+        }
+      }
+      __syncthreads();
+      const int k = k4;
+      if constexpr (KPT == 1) {
+        float wn = 0.f;
+        if (row < p) {
+          float b = 0.f;
+#pragma unroll 8
+          for (int l = 0; l < RP; ++l) b = fmaf(Ws[i * RP + l], Gs[l * KC + k4], b);
+          wn = (b > 0.f) ? w1 * (a1[0] / b) : w1;
+          Wp[row * RP + k] = wn;
+          if (k < r) Wc[row * r + k] = wn;
+          if (WT) WT[(int64_t)k * ldwt + row] = wn;
+          if (WbT) WbT[(int64_t)k * ldwt + row] = to_bf16(wn);
+        }
+        Wn[i * RP + k] = bf16 ? bf16_val(wn) : wn;
+      } else {
+        float4 wn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < p) {
+          const float4 a = a4[0];
+          float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
+#pragma unroll 8
+          for (int l = 0; l < RP; ++l) {
+            const float wl = Ws[i * RP + l];
+            const float4 g4 = *reinterpret_cast<const float4*>(&Gs[l * KC + k4]);
+            b0 = fmaf(wl, g4.x, b0);
+            b1 = fmaf(wl, g4.y, b1);
+            b2 = fmaf(wl, g4.z, b2);
+            b3 = fmaf(wl, g4.w, b3);
+          }
+          const float4 w = wt;
+          wn.x = (b0 > 0.f) ? w.x * (a.x / b0) : w.x;
+          wn.y = (b1 > 0.f) ? w.y * (a.y / b1) : w.y;
+          wn.z = (b2 > 0.f) ? w.z * (a.z / b2) : w.z;
+          wn.w = (b3 > 0.f) ? w.w * (a.w / b3) : w.w;
+          *reinterpret_cast<float4*>(&Wp[row * RP + k]) = wn;
+          const float wv[4] = {wn.x, wn.y, wn.z, wn.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (k + e < r) Wc[row * r + k + e] = wv[e];
+            if (WT) WT[(int64_t)(k + e) * ldwt + row] = wv[e];
+            if (WbT) WbT[(int64_t)(k + e) * ldwt + row] = to_bf16(wv[e]);
+          }
+        }
+        if (bf16) {
+          wn.x = bf16_val(wn.x); wn.y = bf16_val(wn.y); wn.z = bf16_val(wn.z); wn.w = bf16_val(wn.w);
+        }
+        *reinterpret_cast<float4*>(&Wn[i * RP + k]) = wn;
+      }
+    } else {
     __syncthreads();
     for (int idx = tid; idx < ROWS * RP / 4; idx += 256) {
       const int ii = idx / (RP / 4), l4 = 4 * (idx % (RP / 4));
@@ -772,6 +904,7 @@ __global__ __launch_bounds__(256) void k_update_w(
         }
       }
     }
+    }
     if (gram) {
       __syncthreads();
 #pragma unroll 4
@@ -833,6 +966,103 @@ __global__ __launch_bounds__(256) void k_update_h(
 
   for (int64_t blk = blockIdx.x; blk * COLS < n; blk += gridDim.x) {
     const int64_t j0 = blk * COLS;
+    if (FUSE && !gram_only) {
+      // All global loads of the column block are issued before the first
+      // wait: the block of H (NI float4 per thread; KC == RP, so entry e of
+      // a thread is also the item it updates), its split sums and, on the
+      // first block, G.
+      constexpr int NQ = RP * COLS / 4;
+      constexpr int NI = (NQ + 255) / 256;
+      constexpr int NG = (RP * RP / 4 + 255) / 256;
+      constexpr int B = NI >= 4 ? 4 : 16 / NI;
+      const bool first = blk == blockIdx.x;
+      float4 hr[NI], sv[NI], gq[NG];
+      int64_t off[NI];
+      bool ok[NI];
+#pragma unroll
+      for (int e = 0; e < NI; ++e) {
+        const int idx = tid + 256 * e;
+        const int kk = idx / (COLS / 4), j4 = 4 * (idx % (COLS / 4));
+        ok[e] = (NQ % 256 == 0 || idx < NQ) && j0 + j4 < n;
+        off[e] = (int64_t)kk * ldp + j0 + j4;
+        hr[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok[e]) hr[e] = *reinterpret_cast<const float4*>(&Hp[(int64_t)kk * ldh + j0 + j4]);
+      }
+#pragma unroll
+      for (int e = 0; e < NG; ++e) {
+        const int idx = tid + 256 * e;
+        gq[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (first && idx < RP * RP / 4) gq[e] = *reinterpret_cast<const float4*>(&G[4 * idx]);
+      }
+      sum_splits_batch<NI, B>(part, off, ok, sp, splits, sv);
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < NI; ++e) {
+        const int idx = tid + 256 * e;
+        if (NQ % 256 == 0 || idx < NQ) {
+          const int kk = idx / (COLS / 4), j4 = 4 * (idx % (COLS / 4));
+          float4 h = hr[e];
+          if (bf16) {
+            h.x = bf16_val(h.x); h.y = bf16_val(h.y); h.z = bf16_val(h.z); h.w = bf16_val(h.w);
+          }
+          *reinterpret_cast<float4*>(&Hs[kk * COLS + j4]) = h;
+        }
+      }
+      if (first) {
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+          const int idx = tid + 256 * e;
+          float4 gv = gq[e];
+          if (bf16) {
+            gv.x = bf16_val(gv.x); gv.y = bf16_val(gv.y); gv.z = bf16_val(gv.z); gv.w = bf16_val(gv.w);
+          }
+          if (idx < RP * RP / 4) *reinterpret_cast<float4*>(&Gs[4 * idx]) = gv;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < NI; ++e) {
+        const int idx = tid + 256 * e;
+        if (NQ % 256 != 0 && idx >= NQ) continue;
+        const int kk = idx / (COLS / 4), j4 = 4 * (idx % (COLS / 4));
+        const int64_t j = j0 + j4;
+        const int k = kk;
+        float4 hn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok[e]) {
+          float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+#pragma unroll 8
+          for (int l = 0; l < RP; ++l) {
+            const float gl_ = Gs[kk * RP + l];
+            const float4 h4 = *reinterpret_cast<const float4*>(&Hs[l * COLS + j4]);
+            d0 = fmaf(gl_, h4.x, d0);
+            d1 = fmaf(gl_, h4.y, d1);
+            d2 = fmaf(gl_, h4.z, d2);
+            d3 = fmaf(gl_, h4.w, d3);
+          }
+          const float4 sum = sv[e], h = hr[e];
+          hn.x = (d0 > 0.f) ? h.x * (sum.x / d0) : h.x;
+          hn.y = (d1 > 0.f) ? h.y * (sum.y / d1) : h.y;
+          hn.z = (d2 > 0.f) ? h.z * (sum.z / d2) : h.z;
+          hn.w = (d3 > 0.f) ? h.w * (sum.w / d3) : h.w;
+          *reinterpret_cast<float4*>(&Hp[(int64_t)k * ldh + j]) = hn;
+          const float hv[4] = {hn.x, hn.y, hn.z, hn.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (j + u < n) {
+              if (k < r) Hc[(int64_t)k * n + j + u] = hv[u];
+              if (Hb) Hb[(int64_t)k * ldh + j + u] = to_bf16(hv[u]);
+            }
+          }
+        }
+        if (bf16) {
+          hn.x = bf16_val(hn.x); hn.y = bf16_val(hn.y); hn.z = bf16_val(hn.z); hn.w = bf16_val(hn.w);
+        }
+        HnT[(j4 + 0) * HP + k] = hn.x;
+        HnT[(j4 + 1) * HP + k] = hn.y;
+        HnT[(j4 + 2) * HP + k] = hn.z;
+        HnT[(j4 + 3) * HP + k] = hn.w;
+      }
+    } else {
     __syncthreads();
     for (int idx = tid; idx < RP * COLS / 4; idx += 256) {
       const int l = idx / (COLS / 4), jj = 4 * (idx % (COLS / 4));
@@ -904,6 +1134,7 @@ __global__ __launch_bounds__(256) void k_update_h(
           }
         }
       }
+    }
     }
     if (gram) {
       __syncthreads();
@@ -1501,6 +1732,14 @@ static const DmaEntry kDma[] = {
     DME(2, 4, 2, 2, 3),  // 6: 64 x 128   pass 2, r <= 64
     DME(2, 4, 4, 1, 4),  // 7: 128 x 64, 4 stages
     DME(2, 4, 2, 2, 4),  // 8: 64 x 128, 4 stages
+    // narrow tiles for problems whose default tiling leaves fewer than 256
+    // workgroups (1024 waves: one per SIMD)
+    DME(1, 4, 4, 1, 3),  // 9:  64 x 64    pass 1, r <= 64
+    DME(2, 2, 2, 2, 3),  // 10: 64 x 64    pass 2, r <= 64
+    DME(1, 2, 4, 1, 3),  // 11: 64 x 32    pass 1, r <= 32
+    DME(1, 2, 2, 2, 3),  // 12: 32 x 64    pass 2, r <= 32
+    DME(2, 1, 2, 1, 3),  // 13: 64 x 16    pass 1, r <= 16
+    DME(1, 2, 1, 2, 3),  // 14: 16 x 64    pass 2, r <= 16
 };
 #undef DME
 static const int kDmaCount = sizeof(kDma) / sizeof(kDma[0]);
@@ -1515,8 +1754,12 @@ DmaCfg dma_config_by_id(int id) {
   return c;
 }
 
-DmaCfg dma_config(int rp, bool pass1) {
+DmaCfg dma_config(int rp, bool pass1, bool narrow) {
   if (rp > 64) return dma_config_by_id(3);
+  if (narrow) {
+    if (pass1) return dma_config_by_id(rp == 16 ? 13 : rp == 32 ? 11 : 9);
+    return dma_config_by_id(rp == 16 ? 14 : rp == 32 ? 12 : 10);
+  }
   if (pass1) return dma_config_by_id(rp == 16 ? 0 : rp == 32 ? 1 : 2);
   return dma_config_by_id(rp == 16 ? 4 : rp == 32 ? 5 : 6);
 }
@@ -1566,8 +1809,8 @@ int update_w_kpt(int rp, int64_t p) {
   return (p + per4 - 1) / per4 >= 256 ? 4 : 1;
 }
 
-int update_grid(int rp, int64_t extent, int cap) {
-  const int64_t per = update_w_kpt(rp, extent) * 256 / (rp < 64 ? rp : 64);  // rows per block
+int update_grid(int rp, int64_t extent, int cap, int kpt) {
+  const int64_t per = kpt * 256 / (rp < 64 ? rp : 64);  // rows per block
   int64_t blocks = (extent + per - 1) / per;
   if (cap > 0 && blocks > cap) blocks = cap;
   return (int)(blocks < 1 ? 1 : blocks);
@@ -1581,8 +1824,7 @@ int update_h_cols(int64_t n) {
   return 16;
 }
 
-int update_h_grid(int64_t n, int cap) {
-  const int cols = update_h_cols(n);
+int update_h_grid(int64_t n, int cap, int cols) {
   int64_t blocks = (n + cols - 1) / cols;
   if (cap > 0 && blocks > cap) blocks = cap;
   return (int)(blocks < 1 ? 1 : blocks);
@@ -1591,10 +1833,10 @@ int update_h_grid(int64_t n, int cap) {
 hipError_t launch_update_w(int rp, int64_t p, int r, const float* part, int64_t ldp, int64_t sp,
                            int splits, const float* G, float* Wp, float* Wcaller, float* WT,
                            uint16_t* WbT, int64_t ldwt, bool bf16, float* gout, int grid,
-                           bool gram_only, hipStream_t st) {
+                           int kpt, bool gram_only, hipStream_t st) {
 #define UW(R)                                                                                  \
   do {                                                                                          \
-    if (update_w_kpt(R, p) == 4)                                                                \
+    if (kpt == 4)                                                                               \
       hipLaunchKernelGGL((k_update_w<R, 4>), dim3(grid), dim3(256), 0, st, p, r, part, ldp, sp,   \
                          splits, G, Wp, Wcaller, WT, WbT, ldwt, (int)bf16, gout, (int)gram_only); \
     else                                                                                        \
@@ -1608,11 +1850,10 @@ hipError_t launch_update_w(int rp, int64_t p, int r, const float* part, int64_t 
 
 hipError_t launch_update_h(int rp, int64_t n, int r, const float* part, int64_t ldp, int64_t sp,
                            int splits, const float* G, float* Hp, int64_t ldh, float* Hcaller,
-                           uint16_t* Hb, bool bf16, float* gout, int grid, bool gram_only,
-                           hipStream_t st) {
+                           uint16_t* Hb, bool bf16, float* gout, int grid, int cols,
+                           bool gram_only, hipStream_t st) {
 #define UH(R)                                                                                  \
   do {                                                                                          \
-    const int cols = update_h_cols(n);                                                          \
     if (cols == 64)                                                                             \
       hipLaunchKernelGGL((k_update_h<R, 64>), dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, \
                          splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only);     \

@@ -38,7 +38,7 @@ using namespace nmfk;
 namespace {
 
 constexpr int64_t kMaxDim = 4000000;  // objective grid.y = ceil(p / 64) <= 65535
-constexpr int32_t kGraphChunk = 16;    // iterations per replay of the large graph
+constexpr int kGraphLevels = 5;        // graphs of 1, 2, 4, 8 and 16 iterations
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -120,7 +120,6 @@ struct nmf_ctx {
   float* gpw = nullptr;  // per-workgroup Grams of W from the W update (fused path)
   float* gph = nullptr;  // per-workgroup Grams of H from the H update (fused path)
   double* fpart = nullptr;
-  double* fdev = nullptr;
   uint32_t* flag = nullptr;   // [0] validation, [1] refit maximum
   double* lsinv = nullptr;    // (G_H + delta I)^-1 for nmf_refit_w
   float* VT = nullptr;
@@ -129,11 +128,14 @@ struct nmf_ctx {
   uint16_t* VTb = nullptr;
   uint16_t* Hb = nullptr;
   uint16_t* WbT = nullptr;
-  double* hostbuf = nullptr;  // pinned, 2 doubles
+  double* hostbuf = nullptr;  // pinned, coherent, 4 doubles: [0] reads, [2..3] checks
+  double* hostbuf_dev = nullptr;  // the same memory as the device addresses it
+  hipEvent_t chk_ev[2] = {nullptr, nullptr};  // solve: check copies landed
 
   bool bf16 = false;
   bool fuse = false;      // rp <= 64: Grams formed in the update kernels
   int uw_grid = 1, uh_grid = 1;
+  int uw_kpt = 4, uh_cols = 64;  // block shapes of the update kernels
   DmaCfg d1{}, d2{};      // the two V-streaming products
   NtCfg cgh{};            // separate Gram products (rp > 64)
   TnCfg cgw{};
@@ -141,9 +143,9 @@ struct nmf_ctx {
   int64_t nparts = 0;
   double nv2 = 0.0;  // ||V||_F^2 in float64
 
-  // captured iterations (use_graph): graphs of 1 and kGraphChunk iterations
+  // captured iterations (use_graph): graph j runs 2^j iterations
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t g1 = nullptr, gk = nullptr;
+  hipGraphExec_t gp[kGraphLevels] = {};
 
   // stage profiler (HIP events on st)
   bool prof = false;
@@ -248,7 +250,7 @@ nmf_status half_w(nmf_ctx* c) {
     TRY_HIP(launch_update_w(c->rp, c->p, c->r, c->part1, c->s1.ldp, c->s1.sp, c->s1.splits,
                             c->GH, c->Wp, c->Wuser, c->bf16 ? nullptr : c->WT,
                             c->bf16 ? c->WbT : nullptr, c->lwt, c->bf16,
-                            c->fuse ? c->gpw : nullptr, c->uw_grid, false, c->st));
+                            c->fuse ? c->gpw : nullptr, c->uw_grid, c->uw_kpt, false, c->st));
   }
   return c->fuse ? NMF_OK : gram_w(c);
 }
@@ -266,20 +268,24 @@ nmf_status half_h(nmf_ctx* c) {
     StageTimer t(c, NMF_STAGE_UPDATE_H);
     TRY_HIP(launch_update_h(c->rp, c->n, c->r, c->part2, c->s2.ldp, c->s2.sp, c->s2.splits,
                             c->GW, c->Hp, c->npad, c->Huser, c->bf16 ? c->Hb : nullptr, c->bf16,
-                            c->fuse ? c->gph : nullptr, c->uh_grid, false, c->st));
+                            c->fuse ? c->gph : nullptr, c->uh_grid, c->uh_cols, false, c->st));
   }
   return c->fuse ? NMF_OK : gram_h(c);
 }
 
-nmf_status objective_async(nmf_ctx* c, const float* Wp) {
+// Objective partials and their float64 reduction into out (device memory,
+// or the mapped pinned host buffer: then no copy operation is needed).
+nmf_status objective_async(nmf_ctx* c, const float* Wp, double* out) {
   StageTimer t(c, NMF_STAGE_OBJECTIVE);
   TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart, c->st));
-  TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, c->fdev, c->st));
+  TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, out, c->st));
   return NMF_OK;
 }
 
-nmf_status read_f(nmf_ctx* c, double* f) {
-  TRY_HIP(hipMemcpyAsync(c->hostbuf, c->fdev, sizeof(double), hipMemcpyDeviceToHost, c->st));
+// Objective of the current state (W = Wp, or 0 for Wp == nullptr), written
+// by the reduction kernel straight into the pinned host buffer.
+nmf_status objective_sync(nmf_ctx* c, const float* Wp, double* f) {
+  TRY(objective_async(c, Wp, c->hostbuf_dev));
   TRY_HIP(hipStreamSynchronize(c->st));
   *f = c->hostbuf[0];
   return NMF_OK;
@@ -288,11 +294,13 @@ nmf_status read_f(nmf_ctx* c, double* f) {
 void free_ctx(nmf_ctx* c) {
   if (!c) return;
   profile_release(c);
-  if (c->g1) (void)hipGraphExecDestroy(c->g1);
-  if (c->gk) (void)hipGraphExecDestroy(c->gk);
+  for (hipGraphExec_t g : c->gp)
+    if (g) (void)hipGraphExecDestroy(g);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->ws) (void)hipFree(c->ws);
   if (c->hostbuf) (void)hipHostFree(c->hostbuf);
+  for (hipEvent_t e : c->chk_ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -358,12 +366,25 @@ nmf_status setup(nmf_ctx* c) {
   const int64_t target2 = env_int("NMF_SPLIT_TARGET2", target);
   const int64_t gtarget = env_int("NMF_GRAM_TARGET", 256);
   const int64_t gmin = env_int("NMF_GRAM_MINSTEPS", 8);
+  // default tiles, or the narrow ones where the default leaves fewer than
+  // 256 workgroups (fewer MFMA waves than SIMDs)
+  auto blocks = [](const Split& sp, const DmaCfg& d, int64_t M, int64_t N) {
+    return (int64_t)sp.splits * ((M + d.bm - 1) / d.bm) * ((N + d.bn - 1) / d.bn);
+  };
   c->d1 = dma_config(rp, true);
   c->d2 = dma_config(rp, false);
   if (env_int("NMF_DMA1", -1) >= 0) c->d1 = dma_config_by_id((int)env_int("NMF_DMA1", 0));
   if (env_int("NMF_DMA2", -1) >= 0) c->d2 = dma_config_by_id((int)env_int("NMF_DMA2", 0));
   c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
   c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
+  if (env_int("NMF_DMA1", -1) < 0 && blocks(c->s1, c->d1, p, rp) < 256) {
+    c->d1 = dma_config(rp, true, true);
+    c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
+  }
+  if (env_int("NMF_DMA2", -1) < 0 && blocks(c->s2, c->d2, rp, n) < 256) {
+    c->d2 = dma_config(rp, false, true);
+    c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
+  }
   c->fuse = rp <= 64;
   if (!c->fuse) {
     if (!c->bf16) {
@@ -379,8 +400,13 @@ nmf_status setup(nmf_ctx* c) {
   }
   c->nparts = objective_parts(p, n);
   const int ucap = c->fuse ? (int)env_int("NMF_UPDATE_CAP", 512) : 0;
-  c->uw_grid = update_grid(rp, p, ucap);
-  c->uh_grid = update_h_grid(n, ucap);
+  c->uw_kpt = update_w_kpt(rp, p);
+  c->uh_cols = update_h_cols(n);
+  const int64_t kpt_env = env_int("NMF_UW_KPT", 0), cols_env = env_int("NMF_UH_COLS", 0);
+  if (kpt_env == 1 || kpt_env == 4) c->uw_kpt = (int)kpt_env;
+  if (cols_env == 16 || cols_env == 32 || cols_env == 64) c->uh_cols = (int)cols_env;
+  c->uw_grid = update_grid(rp, p, ucap, c->uw_kpt);
+  c->uh_grid = update_h_grid(n, ucap, c->uh_cols);
 
   // carve one allocation, 256-byte aligned pieces
   size_t off = 0;
@@ -402,7 +428,6 @@ nmf_status setup(nmf_ctx* c) {
   const size_t ogw = c->fuse ? take(sizeof(float) * (size_t)c->uw_grid * rp * rp) : 0;
   const size_t ogh = c->fuse ? take(sizeof(float) * (size_t)c->uh_grid * rp * rp) : 0;
   const size_t ofp = take(sizeof(double) * (size_t)c->nparts);
-  const size_t ofd = take(sizeof(double) * 2);
   const size_t ofl = take(sizeof(uint32_t) * 4);
   const size_t oli = c->fuse ? take(sizeof(double) * (size_t)rp * rp) : 0;
   size_t oVT = 0, oWT = 0, oVb = 0, oVTb = 0, oHb = 0, oWbT = 0;
@@ -434,7 +459,6 @@ nmf_status setup(nmf_ctx* c) {
     c->gph = reinterpret_cast<float*>(base + ogh);
   }
   c->fpart = reinterpret_cast<double*>(base + ofp);
-  c->fdev = reinterpret_cast<double*>(base + ofd);
   c->flag = reinterpret_cast<uint32_t*>(base + ofl);
   if (c->fuse) c->lsinv = reinterpret_cast<double*>(base + oli);
   if (!c->bf16) {
@@ -446,11 +470,14 @@ nmf_status setup(nmf_ctx* c) {
     c->Hb = reinterpret_cast<uint16_t*>(base + oHb);
     c->WbT = reinterpret_cast<uint16_t*>(base + oWbT);
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->hostbuf), 2 * sizeof(double), 0) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->hostbuf), 4 * sizeof(double),
+                    hipHostMallocCoherent) != hipSuccess) {
     c->hostbuf = nullptr;
     (void)hipGetLastError();
     return NMF_ENOMEM;
   }
+  TRY_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hostbuf_dev), c->hostbuf, 0));
+  for (hipEvent_t& e : c->chk_ev) TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
   // zero the whole workspace (padding must read as zero)
   TRY_HIP(launch_fill_u32(static_cast<uint32_t*>(c->ws), (int64_t)(off / 4), 0u, c->st));
@@ -489,14 +516,13 @@ nmf_status setup(nmf_ctx* c) {
   }
 
   // ||V||_F^2 (objective with W = 0), then the Grams of the start
-  TRY(objective_async(c, nullptr));
-  TRY(read_f(c, &c->nv2));
+  TRY(objective_sync(c, nullptr, &c->nv2));
   if (c->fuse) {
     // per-workgroup Grams of the start; the first products reduce them
     TRY_HIP(launch_update_w(rp, p, c->r, nullptr, 0, 0, 0, nullptr, c->Wp, c->Wuser, nullptr,
-                            nullptr, 0, c->bf16, c->gpw, c->uw_grid, true, c->st));
+                            nullptr, 0, c->bf16, c->gpw, c->uw_grid, c->uw_kpt, true, c->st));
     TRY_HIP(launch_update_h(rp, n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, npad, c->Huser,
-                            nullptr, c->bf16, c->gph, c->uh_grid, true, c->st));
+                            nullptr, c->bf16, c->gph, c->uh_grid, c->uh_cols, true, c->st));
   } else {
     TRY(gram_h(c));
     TRY(gram_w(c));
@@ -584,26 +610,47 @@ nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
     }
     return NMF_OK;
   }
+  // the largest graph while it fits, then the binary digits of the rest
+  // (10 iterations = one launch of 8 and one of 2)
+  constexpr int top = kGraphLevels - 1;
   int32_t left = iters;
-  if (left >= kGraphChunk) {
-    if (!c->gk) TRY(capture(c, kGraphChunk, &c->gk));
-    for (; left >= kGraphChunk; left -= kGraphChunk) TRY_HIP(hipGraphLaunch(c->gk, c->st));
-  }
-  if (left > 0) {
-    if (!c->g1) TRY(capture(c, 1, &c->g1));
-    for (; left > 0; --left) TRY_HIP(hipGraphLaunch(c->g1, c->st));
+  for (int j = top; j >= 0; --j) {
+    const int32_t n = 1 << j;
+    while (left >= n) {
+      if (!c->gp[j]) TRY(capture(c, n, &c->gp[j]));
+      TRY_HIP(hipGraphLaunch(c->gp[j], c->st));
+      left -= n;
+      if (j < top) break;
+    }
   }
   return NMF_OK;
 }
 
 nmf_status nmf_objective(nmf_ctx* c, double* f_host) {
   if (!c || !f_host) return NMF_EINVAL;
-  TRY(objective_async(c, c->Wp));
   double f;
-  TRY(read_f(c, &f));
+  TRY(objective_sync(c, c->Wp, &f));
   *f_host = f;
   return std::isfinite(f) ? NMF_OK : NMF_ENONFINITE;
 }
+
+namespace {
+
+// Objective of the state after everything enqueued so far, written into
+// check slot `slot` (hostbuf[2 + slot]); chk_ev[slot] marks its arrival.
+nmf_status enqueue_check(nmf_ctx* c, int slot) {
+  TRY(objective_async(c, c->Wp, c->hostbuf_dev + 2 + slot));
+  TRY_HIP(hipEventRecord(c->chk_ev[slot], c->st));
+  return NMF_OK;
+}
+
+nmf_status wait_check(nmf_ctx* c, int slot, double* f) {
+  TRY_HIP(hipEventSynchronize(c->chk_ev[slot]));
+  *f = c->hostbuf[2 + slot];
+  return NMF_OK;
+}
+
+}  // namespace
 
 nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double* f_host,
                      double* trace, int32_t trace_len) {
@@ -616,26 +663,52 @@ nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double*
   if (s != NMF_OK) return s;
   int32_t nt = 0;
   if (trace && nt < trace_len) trace[nt++] = f_prev;
-  int32_t k = 0;
-  while (k < max_iters) {
-    const int32_t todo = std::min(c->opt.check_every, max_iters - k);
+  if (max_iters == 0) return NMF_ENOTCONVERGED;
+
+  // Chunks of check_every iterations, each followed by an objective whose
+  // value is copied to the host.  The next chunk and its check are enqueued
+  // before the host waits for the current check, so the device never idles
+  // on the host; the price is that when the rule holds, the chunk already
+  // enqueued after that check also runs (and its objective is the final
+  // one: the value returned always belongs to the factors returned).
+  int32_t queued = 0;         // iterations enqueued
+  int32_t pend_k[2] = {0, 0};  // iterations behind each pending check
+  int head = 0, npend = 0;    // oldest pending slot, pending count
+  auto push = [&]() -> nmf_status {
+    const int32_t todo = std::min(c->opt.check_every, max_iters - queued);
     TRY(nmf_step(c, todo));
-    k += todo;
+    queued += todo;
+    const int slot = (head + npend) & 1;
+    TRY(enqueue_check(c, slot));
+    pend_k[slot] = queued;
+    ++npend;
+    return NMF_OK;
+  };
+  TRY(push());
+  bool done = false;
+  while (npend > 0) {
+    if (!done && queued < max_iters && npend < 2) TRY(push());
     double f;
-    s = nmf_objective(c, &f);
-    *iters_done = k;
+    TRY(wait_check(c, head, &f));
+    *iters_done = pend_k[head];
     *f_host = f;
-    if (s != NMF_OK) return s;
+    head ^= 1;
+    --npend;
     if (trace && nt < trace_len) trace[nt++] = f;
-    bool done;
+    if (!std::isfinite(f)) {
+      s = NMF_ENONFINITE;
+      done = true;
+      continue;  // drain the pending check (its factors are the returned ones)
+    }
+    if (done) continue;
     if (c->opt.tol_kind == NMF_TOL_REL_CHANGE)
       done = std::fabs(f - f_prev) / (std::fabs(f_prev) + 1.0) < c->opt.tol;
     else
       done = (c->nv2 > 0.0 ? f / c->nv2 : 0.0) <= c->opt.tol;
     f_prev = f;
-    if (done) return NMF_OK;
   }
-  return NMF_ENOTCONVERGED;
+  if (s == NMF_ENONFINITE) return s;
+  return done ? NMF_OK : NMF_ENOTCONVERGED;
 }
 
 nmf_status nmf_refit_w(nmf_ctx* c, float floor_rel) {
