@@ -1165,9 +1165,12 @@ __global__ __launch_bounds__(256) void k_update_h(
 // ---------------------------------------------------------------------------
 // Objective partials (eq. nnmf-objfn), direct residual in float64:
 // each 64 x 64 tile accumulates sum (v_ij - sum_k w_ik h_kj)^2 with the
-// inner products formed by float64 FMAs of the float32 factors.  A thread
-// owns a 4 x 4 block; the tile total is reduced in a fixed order.
-// Wp == nullptr means W = 0 (gives ||V||_F^2).
+// inner products formed by float64 FMAs of the float32 factors (exactly
+// converted).  The W block is staged in LDS row-major with a padded pitch
+// (conflict-free stores), H rank-major; a thread owns a 4 x 4 block and
+// loads its V entries first, so their latency overlaps the staging and the
+// products.  The tile total is reduced in a fixed order.  Wp == nullptr
+// means W = 0 (gives ||V||_F^2).
 // ---------------------------------------------------------------------------
 template <int RP>
 __global__ __launch_bounds__(256) void k_objective(
@@ -1175,11 +1178,16 @@ __global__ __launch_bounds__(256) void k_objective(
     const float* __restrict__ Wp, const float* __restrict__ Hp, int64_t ldh,
     double* __restrict__ part) {
   constexpr int KC = RP < 64 ? RP : 64;
-  __shared__ __attribute__((aligned(16))) float WsT[KC * 64];
+  constexpr int WP = KC + 4;  // W row pitch (16-byte aligned rows)
+  __shared__ __attribute__((aligned(16))) float Ws[64 * WP];
   __shared__ __attribute__((aligned(16))) float Hs[KC * 64];
   __shared__ double red[4];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int64_t j0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
+
+  float4 vq[4];  // this thread's 4 x 4 block of V
+#pragma unroll
+  for (int a = 0; a < 4; ++a) vq[a] = load4(V, ldv, i0 + 4 * ty + a, p, j0 + 4 * tx, n);
 
   double s[4][4];
 #pragma unroll
@@ -1190,21 +1198,26 @@ __global__ __launch_bounds__(256) void k_objective(
   if (Wp) {
     for (int kc0 = 0; kc0 < RP; kc0 += KC) {
       __syncthreads();
-      for (int idx = tid; idx < 64 * KC; idx += 256) {
-        const int ii = idx / KC, kk = idx % KC;
-        WsT[kk * 64 + ii] = Wp[(i0 + ii) * RP + kc0 + kk];
+      for (int idx = tid; idx < 64 * KC / 4; idx += 256) {
+        const int ii = idx / (KC / 4), k4 = 4 * (idx % (KC / 4));
+        const float4 w = *reinterpret_cast<const float4*>(&Wp[(i0 + ii) * RP + kc0 + k4]);
+        float* d = &Ws[ii * WP + k4];
+        d[0] = w.x; d[1] = w.y; d[2] = w.z; d[3] = w.w;
       }
-      for (int idx = tid; idx < KC * 64; idx += 256) {
-        const int kk = idx / 64, jj = idx % 64;
-        Hs[idx] = Hp[(int64_t)(kc0 + kk) * ldh + j0 + jj];
+      for (int idx = tid; idx < KC * 64 / 4; idx += 256) {
+        const int kk = idx / 16, j4 = 4 * (idx % 16);
+        const float4 h = *reinterpret_cast<const float4*>(&Hp[(int64_t)(kc0 + kk) * ldh + j0 + j4]);
+        float* d = &Hs[kk * 64 + j4];
+        d[0] = h.x; d[1] = h.y; d[2] = h.z; d[3] = h.w;
       }
       __syncthreads();
 #pragma unroll 4
       for (int kk = 0; kk < KC; ++kk) {
-        const float4 w = *reinterpret_cast<const float4*>(&WsT[kk * 64 + 4 * ty]);
-        const float4 h = *reinterpret_cast<const float4*>(&Hs[kk * 64 + 4 * tx]);
-        const double wd[4] = {(double)w.x, (double)w.y, (double)w.z, (double)w.w};
-        const double hd[4] = {(double)h.x, (double)h.y, (double)h.z, (double)h.w};
+        double wd[4], hd[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) wd[a] = Ws[(4 * ty + a) * WP + kk];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) hd[b] = Hs[kk * 64 + 4 * tx + b];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1218,8 +1231,7 @@ __global__ __launch_bounds__(256) void k_objective(
   for (int a = 0; a < 4; ++a) {
     const int64_t row = i0 + 4 * ty + a;
     const int64_t col = j0 + 4 * tx;
-    const float4 v = load4(V, ldv, row, p, col, n);
-    const float vv[4] = {v.x, v.y, v.z, v.w};
+    const float vv[4] = {vq[a].x, vq[a].y, vq[a].z, vq[a].w};
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       if (row < p && col + b < n) {

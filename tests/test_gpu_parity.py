@@ -289,6 +289,40 @@ def test_full_size_image_like_one_iteration(gpu_lib):
     ctx.close()
 
 
+# The product tiling depends on the problem size: below 256 workgroups the
+# 64-wide tiles, above it the default 128-row / 128-column ones.  The cases
+# above are small (64-wide tiles); 2048 x 4096 has 256 workgroups in both
+# products with the default tiles, for every padded rank <= 64.
+@pytest.mark.parametrize("r", [12, 32, 64])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_default_tiles_mid_size(gpu_lib, r, precision):
+    V, W0, H0 = g.image_like(2048, 4096, r, seed=70 + r, init_seed=71 + r)
+    if precision == "bf16":
+        V = V + np.float32(1e-3)  # no exact zeros in the factors (relative errors)
+    ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0, precision=precision)
+    iters = 4
+    if precision == "fp32":
+        Wo, Ho, tr = o.run(V, W0, H0, iters)
+        fs = [ctx.objective()]
+        for _ in range(iters):
+            ctx.step(1)
+            fs.append(ctx.objective())
+        assert np.max(np.abs(np.array(fs) - tr) / tr) < 1e-5
+        assert frob_rel(host(Wd), Wo) < 1e-4
+        assert frob_rel(host(Hd), Ho) < 1e-4
+    else:
+        for _ in range(iters):
+            Win, Hin = host(Wd), host(Hd)
+            ctx.update_w()
+            err = np.abs(host(Wd) - o.update_w(V, Win, Hin, bf16=True))
+            assert np.median(err / host(Wd)) < 1e-5 and np.max(err / host(Wd)) < 2e-3
+            Win = host(Wd)
+            ctx.update_h()
+            err = np.abs(host(Hd) - o.update_h(V, Win, Hin, bf16=True))
+            assert np.median(err / host(Hd)) < 1e-5 and np.max(err / host(Hd)) < 2e-3
+    ctx.close()
+
+
 # ------------------------------------------------------------------ BF16 tier
 # The BF16 tier rounds every product operand (V, W, H and the r x r Grams) to
 # bfloat16 (RNE) and accumulates in float32 with float32 master factors.  The
@@ -336,13 +370,14 @@ def test_bf16_objective_close_to_fp64_after_many_iterations(gpu_lib):
 
 
 def test_graph_replay_matches_direct_launches(gpu_lib):
-    """nmf_step replays captured graphs (16-iteration and 1-iteration); every
-    replay, interleaved with eager work (objective, half-steps), must give the
-    same bits as direct launches."""
+    """nmf_step replays captured graphs of 16, 8, 4, 2 and 1 iterations (37 =
+    16 + 16 + 4 + 1, 5 = 4 + 1, 10 = 8 + 2); every replay, interleaved with
+    eager work (objective, half-steps), must give the same bits as direct
+    launches."""
     V, W0, H0 = g.image_like(600, 1100, 24, seed=61, init_seed=62)
     a, _, Wa, Ha = make(gpu_lib, V, W0, H0, use_graph=True)
     b, _, Wb, Hb = make(gpu_lib, V, W0, H0, use_graph=False)
-    for iters in (37, 1, 16, 5):
+    for iters in (37, 1, 16, 5, 10):
         a.step(iters)
         b.step(iters)
         fa, fb = a.objective(), b.objective()
