@@ -703,7 +703,8 @@ __global__ __launch_bounds__(256) void k_update_w(
   constexpr int ROWS = 256 * KPT / KC;    // KPT rank entries per thread (4, or 1 for small p)
   constexpr bool FUSE = RP <= 64;         // Gram partial fits one thread tile
   constexpr int TB = RP / 16;             // Gram tile per thread: TB x TB
-  __shared__ __attribute__((aligned(16))) float Ws[ROWS * RP];
+  constexpr int WSP = RP + 4;             // padded row pitch: the 4 rows a wave reads sit in distinct banks
+  __shared__ __attribute__((aligned(16))) float Ws[ROWS * WSP];
   __shared__ __attribute__((aligned(16))) float Gs[RP * KC];
   __shared__ __attribute__((aligned(16))) float Wn[FUSE ? ROWS * RP : 4];
   const int tid = threadIdx.x;
@@ -755,7 +756,7 @@ __global__ __launch_bounds__(256) void k_update_w(
         if (bf16) {
           w.x = bf16_val(w.x); w.y = bf16_val(w.y); w.z = bf16_val(w.z); w.w = bf16_val(w.w);
         }
-        *reinterpret_cast<float4*>(&Ws[ti * RP + tl4]) = w;
+        *reinterpret_cast<float4*>(&Ws[ti * WSP + tl4]) = w;
       }
       if (first) {
 #pragma unroll
@@ -775,7 +776,7 @@ __global__ __launch_bounds__(256) void k_update_w(
         if (row < p) {
           float b = 0.f;
 #pragma unroll 8
-          for (int l = 0; l < RP; ++l) b = fmaf(Ws[i * RP + l], Gs[l * KC + k4], b);
+          for (int l = 0; l < RP; ++l) b = fmaf(Ws[i * WSP + l], Gs[l * KC + k4], b);
           wn = (b > 0.f) ? w1 * (a1[0] / b) : w1;
           Wp[row * RP + k] = wn;
           if (k < r) Wc[row * r + k] = wn;
@@ -790,7 +791,7 @@ __global__ __launch_bounds__(256) void k_update_w(
           float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
 #pragma unroll 8
           for (int l = 0; l < RP; ++l) {
-            const float wl = Ws[i * RP + l];
+            const float wl = Ws[i * WSP + l];
             const float4 g4 = *reinterpret_cast<const float4*>(&Gs[l * KC + k4]);
             b0 = fmaf(wl, g4.x, b0);
             b1 = fmaf(wl, g4.y, b1);
@@ -825,7 +826,7 @@ __global__ __launch_bounds__(256) void k_update_w(
       if (bf16) {
         w.x = bf16_val(w.x); w.y = bf16_val(w.y); w.z = bf16_val(w.z); w.w = bf16_val(w.w);
       }
-      *reinterpret_cast<float4*>(&Ws[ii * RP + l4]) = w;
+      *reinterpret_cast<float4*>(&Ws[ii * WSP + l4]) = w;
       if (FUSE && gram_only) *reinterpret_cast<float4*>(&Wn[ii * RP + l4]) = w;
     }
     if (!gram_only) {
@@ -858,7 +859,7 @@ __global__ __launch_bounds__(256) void k_update_w(
             for (; q < splits; ++q) a += part[q * sp + row * ldp + k];
             float b = 0.f;
 #pragma unroll 8
-            for (int l = 0; l < RP; ++l) b = fmaf(Ws[i * RP + l], Gs[l * KC + k4], b);
+            for (int l = 0; l < RP; ++l) b = fmaf(Ws[i * WSP + l], Gs[l * KC + k4], b);
             const float w = Wp[row * RP + k];
             wn = (b > 0.f) ? w * (a / b) : w;
             Wp[row * RP + k] = wn;
@@ -875,7 +876,7 @@ __global__ __launch_bounds__(256) void k_update_w(
           float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
 #pragma unroll 8
           for (int l = 0; l < RP; ++l) {
-            const float wl = Ws[i * RP + l];
+            const float wl = Ws[i * WSP + l];
             const float4 g4 = *reinterpret_cast<const float4*>(&Gs[l * KC + k4]);
             b0 = fmaf(wl, g4.x, b0);
             b1 = fmaf(wl, g4.y, b1);
@@ -1009,6 +1010,8 @@ __global__ __launch_bounds__(256) void k_update_h(
         }
       }
       if (first) {
+        // G transposed (Gs[l][k] = G[k][l]): the items of a wave then read
+        // consecutive words of one row
 #pragma unroll
         for (int e = 0; e < NG; ++e) {
           const int idx = tid + 256 * e;
@@ -1016,10 +1019,36 @@ __global__ __launch_bounds__(256) void k_update_h(
           if (bf16) {
             gv.x = bf16_val(gv.x); gv.y = bf16_val(gv.y); gv.z = bf16_val(gv.z); gv.w = bf16_val(gv.w);
           }
-          if (idx < RP * RP / 4) *reinterpret_cast<float4*>(&Gs[4 * idx]) = gv;
+          if (idx < RP * RP / 4) {
+            const int gk_ = (4 * idx) / RP, gl0 = (4 * idx) % RP;
+            Gs[(gl0 + 0) * RP + gk_] = gv.x;
+            Gs[(gl0 + 1) * RP + gk_] = gv.y;
+            Gs[(gl0 + 2) * RP + gk_] = gv.z;
+            Gs[(gl0 + 3) * RP + gk_] = gv.w;
+          }
         }
       }
       __syncthreads();
+      // denominators of all NI items of this thread at once: they share the
+      // column group j4 (ranks tid / (COLS / 4) + e * 1024 / COLS), so one
+      // read of H serves all of them; each sum still runs over l ascending
+      const int j4t = 4 * (tid % (COLS / 4));
+      float dd[NI][4];
+#pragma unroll
+      for (int e = 0; e < NI; ++e) dd[e][0] = dd[e][1] = dd[e][2] = dd[e][3] = 0.f;
+#pragma unroll 4
+      for (int l = 0; l < RP; ++l) {
+        const float4 h4 = *reinterpret_cast<const float4*>(&Hs[l * COLS + j4t]);
+#pragma unroll
+        for (int e = 0; e < NI; ++e) {
+          const int kk = (tid + 256 * e) / (COLS / 4);
+          const float gl_ = Gs[l * RP + (kk < RP ? kk : 0)];
+          dd[e][0] = fmaf(gl_, h4.x, dd[e][0]);
+          dd[e][1] = fmaf(gl_, h4.y, dd[e][1]);
+          dd[e][2] = fmaf(gl_, h4.z, dd[e][2]);
+          dd[e][3] = fmaf(gl_, h4.w, dd[e][3]);
+        }
+      }
 #pragma unroll
       for (int e = 0; e < NI; ++e) {
         const int idx = tid + 256 * e;
@@ -1029,16 +1058,7 @@ __global__ __launch_bounds__(256) void k_update_h(
         const int k = kk;
         float4 hn = make_float4(0.f, 0.f, 0.f, 0.f);
         if (ok[e]) {
-          float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
-#pragma unroll 8
-          for (int l = 0; l < RP; ++l) {
-            const float gl_ = Gs[kk * RP + l];
-            const float4 h4 = *reinterpret_cast<const float4*>(&Hs[l * COLS + j4]);
-            d0 = fmaf(gl_, h4.x, d0);
-            d1 = fmaf(gl_, h4.y, d1);
-            d2 = fmaf(gl_, h4.z, d2);
-            d3 = fmaf(gl_, h4.w, d3);
-          }
+          const float d0 = dd[e][0], d1 = dd[e][1], d2 = dd[e][2], d3 = dd[e][3];
           const float4 sum = sv[e], h = hr[e];
           hn.x = (d0 > 0.f) ? h.x * (sum.x / d0) : h.x;
           hn.y = (d1 > 0.f) ? h.y * (sum.y / d1) : h.y;
@@ -1159,6 +1179,281 @@ __global__ __launch_bounds__(256) void k_update_h(
     for (int a = 0; a < TB; ++a)
 #pragma unroll
       for (int b = 0; b < TB; ++b) out[(gk + a) * RP + gl + b] = ga[a][b];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Update epilogues with the denominators on the matrix cores: the H update
+// at padded ranks 128 and 256, the W update at 256 (at 128 the vector-unit
+// W update above measured faster).  At these ranks W (H H^T) and (W^T W) H
+// are dense products (K = rp), so they are formed by MFMA from LDS-staged
+// operands in chunks of 128 bytes of K:
+//   D (M x N) = A (M x K) * B (K x N), A staged row-major, B transposed
+// (one 128-byte row per output column), 16-byte chunk q of row t stored at
+// slot q ^ (t % 8) as in the V passes.  FP32: v_mfma_f32_16x16x4_f32 on the
+// float32 operands; BF16 tier: v_mfma_f32_16x16x32_bf16 on their bfloat16
+// roundings (the operands the tier's products use), float32 accumulation.
+// ---------------------------------------------------------------------------
+
+// 16-byte chunk slot of element e (of ES bytes) in staged row t
+template <int ES>
+__device__ __forceinline__ int stage_off(int t, int e) {
+  constexpr int PER = 16 / ES;  // elements per chunk
+  const int q = e / PER;
+  return t * 128 + 16 * (q ^ (t & 7)) + (e % PER) * ES;
+}
+
+template <bool BF>
+__device__ __forceinline__ void stage_put(char* lds, int t, int e, float v) {
+  if constexpr (BF) {
+    *reinterpret_cast<uint16_t*>(lds + stage_off<2>(t, e)) = to_bf16(v);
+  } else {
+    *reinterpret_cast<float*>(lds + stage_off<4>(t, e)) = v;
+  }
+}
+
+// acc[i][j] += A rows (a0 + 16 i + c) x B^T rows (b0 + 16 j + c) over one
+// staged chunk (KE = 128 / ES elements of K).
+template <int MI, int NJ, bool BF>
+__device__ __forceinline__ void mma_chunk(const char* A, int a0, const char* Bt, int b0,
+                                          v4f (&acc)[MI][NJ]) {
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const int q = 4 * kk + g;
+    const int off = 16 * (q ^ (c & 7));
+    if constexpr (BF) {
+      v8bf a[MI], b[NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[i] = *reinterpret_cast<const v8bf*>(A + (a0 + 16 * i + c) * 128 + off);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = *reinterpret_cast<const v8bf*>(Bt + (b0 + 16 * j + c) * 128 + off);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+    } else {
+      v4f a[MI], b[NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[i] = *reinterpret_cast<const v4f*>(A + (a0 + 16 * i + c) * 128 + off);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = *reinterpret_cast<const v4f*>(Bt + (b0 + 16 * j + c) * 128 + off);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) acc[i][j] = mfma_f32(a[i][t], b[j][t], acc[i][j]);
+    }
+  }
+}
+
+// W half-step, rp in {128, 256}: a block of 64 WR threads x 4 waves along
+// the ranks takes ROWS = 32 WR rows of W (grid-stride);
+// D = W_rows (ROWS x rp) * G (rp x rp).  Wave (wr, wc) ends with
+// D[i0 + 32 wr + 16 ib + 4 g + v][wc rp/4 + 16 kb + c].
+template <int RP, int WR, bool BF>
+__global__ __launch_bounds__(256 * WR) void k_update_w_mma(
+    int64_t p, int r, const float* __restrict__ part, int64_t ldp, int64_t sp, int splits,
+    const float* __restrict__ G, float* __restrict__ Wp, float* __restrict__ Wc,
+    float* __restrict__ WT, uint16_t* __restrict__ WbT, int64_t ldwt) {
+  constexpr int ES = BF ? 2 : 4, KE = 128 / ES, T = 256 * WR;
+  constexpr int ROWS = 32 * WR, MI = 2, NJ = RP / 64;
+  __shared__ __attribute__((aligned(1024))) char As[ROWS * 128];
+  __shared__ __attribute__((aligned(1024))) char Bs[RP * 128];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int wc = wave & 3, wr = wave >> 2;
+  const int kb = wc * (RP / 4), ib = 32 * wr;
+  for (int64_t blk = blockIdx.x; blk * ROWS < p; blk += gridDim.x) {
+    const int64_t i0 = blk * ROWS;
+    v4f acc[MI][NJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int l0 = 0; l0 < RP; l0 += KE) {
+      __syncthreads();
+      // A: rows i0 .. i0 + ROWS of W (ppad rows, zero beyond p), columns l0 ..
+      for (int idx = tid; idx < ROWS * KE / 4; idx += T) {
+        const int t = idx / (KE / 4), e4 = 4 * (idx % (KE / 4));
+        const float4 w = *reinterpret_cast<const float4*>(&Wp[(i0 + t) * RP + l0 + e4]);
+        stage_put<BF>(As, t, e4 + 0, w.x);
+        stage_put<BF>(As, t, e4 + 1, w.y);
+        stage_put<BF>(As, t, e4 + 2, w.z);
+        stage_put<BF>(As, t, e4 + 3, w.w);
+      }
+      // B^T: row k holds G[l0 .. l0 + KE][k]
+      for (int idx = tid; idx < KE * RP / 4; idx += T) {
+        const int e = idx / (RP / 4), k4 = 4 * (idx % (RP / 4));
+        const float4 gv = *reinterpret_cast<const float4*>(&G[(int64_t)(l0 + e) * RP + k4]);
+        stage_put<BF>(Bs, k4 + 0, e, gv.x);
+        stage_put<BF>(Bs, k4 + 1, e, gv.y);
+        stage_put<BF>(Bs, k4 + 2, e, gv.z);
+        stage_put<BF>(Bs, k4 + 3, e, gv.w);
+      }
+      __syncthreads();
+      mma_chunk<MI, NJ, BF>(As, ib, Bs, kb, acc);
+    }
+    // ratio update; the numerators are summed over the splits in ascending
+    // order, all of this lane's entries of one split loaded together
+    float na[MI][NJ][4];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) na[i][j][v] = 0.f;
+    for (int q = 0; q < splits; ++q) {
+      float x[MI][NJ][4];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t row = i0 + ib + 16 * i + 4 * g + v;
+            x[i][j][v] = 0.f;
+            if (row < p) x[i][j][v] = part[q * sp + row * ldp + kb + 16 * j + c];
+          }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) na[i][j][v] += x[i][j][v];
+    }
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int k = kb + 16 * j + c;
+        float wv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = i0 + ib + 16 * i + 4 * g + v;
+          wv[v] = 0.f;
+          if (row >= p) continue;
+          const float a = na[i][j][v];
+          const float b = acc[i][j][v];
+          const float w = Wp[row * RP + k];
+          const float wn = (b > 0.f) ? w * (a / b) : w;
+          Wp[row * RP + k] = wn;
+          if (k < r) Wc[row * r + k] = wn;
+          wv[v] = wn;
+        }
+        const int64_t rb = i0 + ib + 16 * i + 4 * g;  // 4 consecutive rows: one store
+        if (rb + 3 < p) {
+          if (WT) *reinterpret_cast<float4*>(&WT[(int64_t)k * ldwt + rb]) = make_float4(wv[0], wv[1], wv[2], wv[3]);
+          if (WbT) {
+            const uint2 h = make_uint2((uint32_t)to_bf16(wv[0]) | ((uint32_t)to_bf16(wv[1]) << 16),
+                                       (uint32_t)to_bf16(wv[2]) | ((uint32_t)to_bf16(wv[3]) << 16));
+            *reinterpret_cast<uint2*>(&WbT[(int64_t)k * ldwt + rb]) = h;
+          }
+        } else {
+          for (int v = 0; v < 4; ++v)
+            if (rb + v < p) {
+              if (WT) WT[(int64_t)k * ldwt + rb + v] = wv[v];
+              if (WbT) WbT[(int64_t)k * ldwt + rb + v] = to_bf16(wv[v]);
+            }
+        }
+      }
+  }
+}
+
+// H half-step, rp in {128, 256}: a block of 4 waves along the ranks x WC
+// along the columns takes COLS = 64 WC columns of H (grid-stride);
+// D = G (rp x rp) * H_cols (rp x COLS).  Wave (wr, wc) ends with
+// D[wr rp/4 + 16 kb + 4 g + v][j0 + 64 wc + 16 jb + c].
+template <int RP, int WC, bool BF>
+__global__ __launch_bounds__(256 * WC) void k_update_h_mma(
+    int64_t n, int r, const float* __restrict__ part, int64_t ldp, int64_t sp, int splits,
+    const float* __restrict__ G, float* __restrict__ Hp, int64_t ldh, float* __restrict__ Hc,
+    uint16_t* __restrict__ Hb) {
+  constexpr int ES = BF ? 2 : 4, KE = 128 / ES, T = 256 * WC;
+  constexpr int COLS = 64 * WC, MI = RP / 64, NJ = 4;
+  __shared__ __attribute__((aligned(1024))) char As[RP * 128];
+  __shared__ __attribute__((aligned(1024))) char Bs[COLS * 128];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int wr = wave & 3, wc = wave >> 2;
+  const int kb = wr * (RP / 4), jb0 = 64 * wc;
+  for (int64_t blk = blockIdx.x; blk * COLS < n; blk += gridDim.x) {
+    const int64_t j0 = blk * COLS;
+    v4f acc[MI][NJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int l0 = 0; l0 < RP; l0 += KE) {
+      __syncthreads();
+      // A: rows of G, columns l0 ..
+      for (int idx = tid; idx < RP * KE / 4; idx += T) {
+        const int t = idx / (KE / 4), e4 = 4 * (idx % (KE / 4));
+        const float4 gv = *reinterpret_cast<const float4*>(&G[(int64_t)t * RP + l0 + e4]);
+        stage_put<BF>(As, t, e4 + 0, gv.x);
+        stage_put<BF>(As, t, e4 + 1, gv.y);
+        stage_put<BF>(As, t, e4 + 2, gv.z);
+        stage_put<BF>(As, t, e4 + 3, gv.w);
+      }
+      // B^T: row jj holds H[l0 .. l0 + KE][j0 + jj] (H is rp x ldh, zero-padded)
+      for (int idx = tid; idx < KE * COLS / 4; idx += T) {
+        const int e = idx / (COLS / 4), j4 = 4 * (idx % (COLS / 4));
+        const float4 h = *reinterpret_cast<const float4*>(&Hp[(int64_t)(l0 + e) * ldh + j0 + j4]);
+        stage_put<BF>(Bs, j4 + 0, e, h.x);
+        stage_put<BF>(Bs, j4 + 1, e, h.y);
+        stage_put<BF>(Bs, j4 + 2, e, h.z);
+        stage_put<BF>(Bs, j4 + 3, e, h.w);
+      }
+      __syncthreads();
+      mma_chunk<MI, NJ, BF>(As, kb, Bs, jb0, acc);
+    }
+    // numerators summed over the splits in ascending order, all of this
+    // lane's entries of one split loaded together
+    float ns[MI][NJ][4];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NJ; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ns[i][jb][v] = 0.f;
+    for (int q = 0; q < splits; ++q) {
+      float x[MI][NJ][4];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int jb = 0; jb < NJ; ++jb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t j = j0 + jb0 + 16 * jb + c;
+            x[i][jb][v] = 0.f;
+            if (j < n) x[i][jb][v] = part[q * sp + (int64_t)(kb + 16 * i + 4 * g + v) * ldp + j];
+          }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int jb = 0; jb < NJ; ++jb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ns[i][jb][v] += x[i][jb][v];
+    }
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NJ; ++jb) {
+        const int64_t j = j0 + jb0 + 16 * jb + c;
+        if (j >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = kb + 16 * i + 4 * g + v;
+          const float s = ns[i][jb][v];
+          const float d = acc[i][jb][v];
+          const float h = Hp[(int64_t)k * ldh + j];
+          const float hn = (d > 0.f) ? h * (s / d) : h;
+          Hp[(int64_t)k * ldh + j] = hn;
+          if (k < r) Hc[(int64_t)k * n + j] = hn;
+          if (Hb) Hb[(int64_t)k * ldh + j] = to_bf16(hn);
+        }
+      }
   }
 }
 
@@ -1752,6 +2047,11 @@ static const DmaEntry kDma[] = {
     DME(1, 2, 2, 2, 3),  // 12: 32 x 64    pass 2, r <= 32
     DME(2, 1, 2, 1, 3),  // 13: 64 x 16    pass 1, r <= 16
     DME(1, 2, 1, 2, 3),  // 14: 16 x 64    pass 2, r <= 16
+    // all 256 ranks in one workgroup (V read once per pass)
+    DME(4, 8, 2, 2, 2),  // 15: 128 x 256  pass 1, r = 256
+    DME(8, 4, 2, 2, 2),  // 16: 256 x 128  pass 2, r = 256
+    DME(4, 8, 2, 2, 3),  // 17: 128 x 256  pass 1, r = 256, 3 stages
+    DME(8, 4, 2, 2, 3),  // 18: 256 x 128  pass 2, r = 256, 3 stages
 };
 #undef DME
 static const int kDmaCount = sizeof(kDma) / sizeof(kDma[0]);
@@ -1846,6 +2146,26 @@ hipError_t launch_update_w(int rp, int64_t p, int r, const float* part, int64_t 
                            int splits, const float* G, float* Wp, float* Wcaller, float* WT,
                            uint16_t* WbT, int64_t ldwt, bool bf16, float* gout, int grid,
                            int kpt, bool gram_only, hipStream_t st) {
+  if (rp == 256) {
+    // matrix-core denominators (no Gram partials at this rank); rank 128
+    // measured faster on the vector units below
+    // 64-row blocks of 8 waves, or 32-row blocks of 4 when p is small
+    const int wr = (p + 63) / 64 >= 256 ? 2 : 1;
+    const dim3 g((unsigned)((p + 32 * wr - 1) / (32 * wr)));
+#define UWM(R, WR)                                                                              \
+  do {                                                                                          \
+    if (bf16)                                                                                   \
+      hipLaunchKernelGGL((k_update_w_mma<R, WR, true>), g, dim3(256 * WR), 0, st, p, r, part,    \
+                         ldp, sp, splits, G, Wp, Wcaller, WT, WbT, ldwt);                       \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_update_w_mma<R, WR, false>), g, dim3(256 * WR), 0, st, p, r, part,   \
+                         ldp, sp, splits, G, Wp, Wcaller, WT, WbT, ldwt);                       \
+  } while (0)
+    if (wr == 2) UWM(256, 2);
+    else UWM(256, 1);
+#undef UWM
+    return hipGetLastError();
+  }
 #define UW(R)                                                                                  \
   do {                                                                                          \
     if (kpt == 4)                                                                               \
@@ -1855,7 +2175,13 @@ hipError_t launch_update_w(int rp, int64_t p, int r, const float* part, int64_t 
       hipLaunchKernelGGL((k_update_w<R, 1>), dim3(grid), dim3(256), 0, st, p, r, part, ldp, sp,   \
                          splits, G, Wp, Wcaller, WT, WbT, ldwt, (int)bf16, gout, (int)gram_only); \
   } while (0)
-  RP_SWITCH(rp, UW)
+  switch (rp) {
+    case 16: UW(16); break;
+    case 32: UW(32); break;
+    case 64: UW(64); break;
+    case 128: UW(128); break;
+    default: return hipErrorInvalidValue;
+  }
 #undef UW
   return hipGetLastError();
 }
@@ -1864,6 +2190,28 @@ hipError_t launch_update_h(int rp, int64_t n, int r, const float* part, int64_t 
                            int splits, const float* G, float* Hp, int64_t ldh, float* Hcaller,
                            uint16_t* Hb, bool bf16, float* gout, int grid, int cols,
                            bool gram_only, hipStream_t st) {
+  if (rp > 64) {
+    // matrix-core denominators (no Gram partials at these ranks);
+    // 128-column blocks of 8 waves, or 64-column blocks of 4 when n is small
+    const int wc = (n + 127) / 128 >= 256 ? 2 : 1;
+    const dim3 g((unsigned)((n + 64 * wc - 1) / (64 * wc)));
+#define UHM(R, WC)                                                                               \
+  do {                                                                                           \
+    if (bf16)                                                                                    \
+      hipLaunchKernelGGL((k_update_h_mma<R, WC, true>), g, dim3(256 * WC), 0, st, n, r, part,    \
+                         ldp, sp, splits, G, Hp, ldh, Hcaller, Hb);                              \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_update_h_mma<R, WC, false>), g, dim3(256 * WC), 0, st, n, r, part,   \
+                         ldp, sp, splits, G, Hp, ldh, Hcaller, Hb);                              \
+  } while (0)
+    if (rp == 128 && wc == 2) UHM(128, 2);
+    else if (rp == 128) UHM(128, 1);
+    else if (rp == 256 && wc == 2) UHM(256, 2);
+    else if (rp == 256) UHM(256, 1);
+    else return hipErrorInvalidValue;
+#undef UHM
+    return hipGetLastError();
+  }
 #define UH(R)                                                                                  \
   do {                                                                                          \
     if (cols == 64)                                                                             \
@@ -1876,7 +2224,12 @@ hipError_t launch_update_h(int rp, int64_t n, int r, const float* part, int64_t 
       hipLaunchKernelGGL((k_update_h<R, 16>), dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, \
                          splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only);     \
   } while (0)
-  RP_SWITCH(rp, UH)
+  switch (rp) {
+    case 16: UH(16); break;
+    case 32: UH(32); break;
+    case 64: UH(64); break;
+    default: return hipErrorInvalidValue;
+  }
 #undef UH
   return hipGetLastError();
 }
