@@ -79,8 +79,9 @@ struct DmaCfg {
   int threads;
 };
 // Tile of the V-streaming products for padded rank rp; narrow: the 64-wide
-// tiles for problems whose default tiling leaves fewer than 256 workgroups.
-DmaCfg dma_config(int rp, bool pass1, bool narrow = false);
+// tiles for problems whose default tiling leaves fewer than 256 workgroups;
+// bf16: the tile for the BF16 tier's products.
+DmaCfg dma_config(int rp, bool pass1, bool narrow = false, bool bf16 = false);
 DmaCfg dma_config_by_id(int id);
 hipError_t launch_nt_dma(const DmaCfg& cfg, bool bf16, const void* X, int64_t ldx,
                          int64_t M, const void* Y, int64_t ldy, int64_t N, int64_t K,

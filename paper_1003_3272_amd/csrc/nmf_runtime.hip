@@ -371,18 +371,18 @@ nmf_status setup(nmf_ctx* c) {
   auto blocks = [](const Split& sp, const DmaCfg& d, int64_t M, int64_t N) {
     return (int64_t)sp.splits * ((M + d.bm - 1) / d.bm) * ((N + d.bn - 1) / d.bn);
   };
-  c->d1 = dma_config(rp, true);
-  c->d2 = dma_config(rp, false);
+  c->d1 = dma_config(rp, true, false, c->bf16);
+  c->d2 = dma_config(rp, false, false, c->bf16);
   if (env_int("NMF_DMA1", -1) >= 0) c->d1 = dma_config_by_id((int)env_int("NMF_DMA1", 0));
   if (env_int("NMF_DMA2", -1) >= 0) c->d2 = dma_config_by_id((int)env_int("NMF_DMA2", 0));
   c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
   c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
   if (env_int("NMF_DMA1", -1) < 0 && blocks(c->s1, c->d1, p, rp) < 256) {
-    c->d1 = dma_config(rp, true, true);
+    c->d1 = dma_config(rp, true, true, c->bf16);
     c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
   }
   if (env_int("NMF_DMA2", -1) < 0 && blocks(c->s2, c->d2, rp, n) < 256) {
-    c->d2 = dma_config(rp, false, true);
+    c->d2 = dma_config(rp, false, true, c->bf16);
     c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
   }
   c->fuse = rp <= 64;
