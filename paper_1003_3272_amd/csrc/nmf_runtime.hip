@@ -9,8 +9,8 @@
 //
 // Internal layout (row-major, zero padded; ppad = round_up(p, 256),
 // npad = round_up(n, 256), rp = padded rank; the streamed copies get row
-// pitches from spread_pitch, i.e. npad / ppad plus 128 bytes when that is a
-// multiple of 4 KB):
+// pitches from spread_pitch, i.e. npad / ppad plus a pad of 128 to 512 bytes
+// when that is a multiple of 4 KB):
 //   Wp (ppad x rp), Hp (rp x npad), G_H and G_W (rp x rp)
 //   FP32:  V itself when p, n are multiples of 256 and its pitch is not a
 //          multiple of 4 KB (else a padded ppad x npad copy),
@@ -351,10 +351,11 @@ nmf_status setup(nmf_ctx* c) {
   const bool need_copy =
       !aligned || (!c->bf16 && (p % 256 != 0 || n % 256 != 0 || bad_pitch));
   // pad of a pitch that is a multiple of 4 KB, per copy (bytes, multiples of
-  // 128; NMF_PAD_V / _VB / _VT override them)
+  // 128, measured per copy at 1024 x 4096 to 8192 x 32768; NMF_PAD_V / _VB /
+  // _VT override them)
   const int64_t pad_v = env_int("NMF_PAD_V", 256) / 128 * 128;
   const int64_t pad_vb = env_int("NMF_PAD_VB", 128) / 128 * 128;
-  const int64_t pad_vt = env_int("NMF_PAD_VT", c->bf16 ? 128 : 256) / 128 * 128;
+  const int64_t pad_vt = env_int("NMF_PAD_VT", 512) / 128 * 128;
   c->ldvk = need_copy ? spread_pitch(npad, 4, pad_v) : c->ldv;
   const int es = c->bf16 ? 2 : 4;
   c->lvb = spread_pitch(npad, 2, pad_vb);
