@@ -13,6 +13,8 @@ Prints one JSON line: iterations/s, the roofline of the dominant kernel
 (from HIP events recorded around every stage inside the timed region) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
 
+Then (unless --no-stream-reference) a plain 1.07 GB device copy by torch, as
+a practical HBM streaming rate beside the 8000 GB/s peak.
 Then (unless --no-precision-tier) the FP32 and BF16 tiers at 8192 x 32768
 for ranks 32, 128 and 256, then (unless --no-batch) the batched tier: 512 problems of uneven shape,
 200 iterations each in one persistent launch, against a loop of the
@@ -52,6 +54,8 @@ def parse():
     ap.add_argument("--ldv-pad", type=int, default=0,
                     help="extra floats per V row in device memory (row-stride experiment)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-tier run")
+    ap.add_argument("--no-stream-reference", action="store_true",
+                    help="skip the reference copy that measures a practical HBM rate")
     ap.add_argument("--no-precision-tier", action="store_true",
                     help="skip the 8192 x 32768 FP32 / BF16 rank sweep")
     ap.add_argument("--pt-iters", type=int, default=200)
@@ -100,6 +104,32 @@ def _gen_matrix(args):
     Wb, m = args
     with threadpool_limits(1):
         return gen.warm_start_matrix(Wb, m)[0]
+
+
+def stream_reference():
+    """Practical streaming rate of this GPU's HBM, beside the 8000 GB/s peak:
+    the best of 10 device-to-device copies of 1.07 GB by torch (bytes read
+    plus written), timed with HIP events.  Context for the roofline
+    fractions, not part of any timed region."""
+    import torch
+    x = torch.rand((8192, 32768), device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(10):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        y.copy_(x)
+        e.record()
+        e.synchronize()
+        best = min(best, s.elapsed_time(e) * 1e-3)
+    nbytes = 2 * x.numel() * 4
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_GBps": round(nbytes / best / 1e9, 1), "bytes": nbytes,
+            "note": "torch device-to-device copy (read + write bytes), best of 10"}
 
 
 def measured_traffic(stage, p, n, r, precision):
@@ -450,6 +480,8 @@ def main():
     }
     del Vd, Wd, Hd
     torch.cuda.empty_cache()
+    if not args.no_stream_reference:
+        out["hbm_reference"] = stream_reference()
     if not args.no_precision_tier:
         out["precision_tier"] = precision_tier_experiment(
             args, lambda msg: print(msg, file=sys.stderr, flush=True))
