@@ -354,7 +354,7 @@ nmf_status setup(nmf_ctx* c) {
   // 128, measured per copy at 1024 x 4096 to 8192 x 32768; NMF_PAD_V / _VB /
   // _VT override them)
   const int64_t pad_v = env_int("NMF_PAD_V", 256) / 128 * 128;
-  const int64_t pad_vb = env_int("NMF_PAD_VB", 128) / 128 * 128;
+  const int64_t pad_vb = env_int("NMF_PAD_VB", 384) / 128 * 128;
   const int64_t pad_vt = env_int("NMF_PAD_VT", 512) / 128 * 128;
   c->ldvk = need_copy ? spread_pitch(npad, 4, pad_v) : c->ldv;
   const int es = c->bf16 ? 2 : 4;
