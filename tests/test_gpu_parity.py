@@ -271,6 +271,28 @@ def test_solve_rel_change_rule_and_cap(gpu_lib):
     ctx.close()
 
 
+def test_solve_reports_nonfinite(gpu_lib):
+    """One entry of V near the float32 maximum (validation off): the float64
+    objective of the start is finite, the float32 products overflow within
+    the first iterations, and solve returns NMF_ENONFINITE with a non-finite
+    f after draining the chunk it had already enqueued."""
+    import ctypes
+    from paper_1003_3272_amd import nmf
+    V, W0, H0 = g.small_uniform()
+    V = V.copy()
+    V[3, 7] = np.float32(3e38)
+    ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0, check_every=5)
+    assert np.isfinite(ctx.objective())
+    it, f = ctypes.c_int32(), ctypes.c_double()
+    st = nmf.load().nmf_solve(ctx._ctx, 50, ctypes.byref(it), ctypes.byref(f), None, 0)
+    assert st == nmf.NMF_ENONFINITE
+    # the chunk whose check first sees the overflow, plus the one behind it
+    assert 10 <= it.value <= 50 and it.value % 5 == 0 and not np.isfinite(f.value)
+    st = nmf.load().nmf_objective(ctx._ctx, ctypes.byref(f))
+    assert st == nmf.NMF_ENONFINITE and not np.isfinite(f.value)
+    ctx.close()
+
+
 # ----------------------------------------------------------- full-size case
 @pytest.mark.slow
 def test_full_size_image_like_one_iteration(gpu_lib):
