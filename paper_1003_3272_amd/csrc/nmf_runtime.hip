@@ -130,7 +130,7 @@ struct nmf_ctx {
   uint16_t* WbT = nullptr;
   double* hostbuf = nullptr;  // pinned, coherent, 4 doubles: [0] reads, [2..3] checks
   double* hostbuf_dev = nullptr;  // the same memory as the device addresses it
-  hipEvent_t chk_ev[2] = {nullptr, nullptr};  // solve: check copies landed
+  hipEvent_t chk_ev[2] = {nullptr, nullptr};  // solve: check values written
 
   bool bf16 = false;
   bool fuse = false;      // rp <= 64: Grams formed in the update kernels
@@ -372,20 +372,24 @@ nmf_status setup(nmf_ctx* c) {
   auto blocks = [](const Split& sp, const DmaCfg& d, int64_t M, int64_t N) {
     return (int64_t)sp.splits * ((M + d.bm - 1) / d.bm) * ((N + d.bn - 1) / d.bn);
   };
+  // A tile must divide the padded row counts of both operands it copies
+  // (the ring reads whole tiles): pass 1 reads ppad rows of V and rp rows of
+  // H, pass 2 rp rows of W^T and npad rows of V^T.  An override that does
+  // not fit is ignored.
+  auto fits1 = [&](const DmaCfg& d) { return ppad % d.bm == 0 && rp % d.bn == 0; };
+  auto fits2 = [&](const DmaCfg& d) { return rp % d.bm == 0 && npad % d.bn == 0; };
   c->d1 = dma_config(rp, true, false, c->bf16);
   c->d2 = dma_config(rp, false, false, c->bf16);
-  if (env_int("NMF_DMA1", -1) >= 0) c->d1 = dma_config_by_id((int)env_int("NMF_DMA1", 0));
-  if (env_int("NMF_DMA2", -1) >= 0) c->d2 = dma_config_by_id((int)env_int("NMF_DMA2", 0));
   c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
   c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
-  if (env_int("NMF_DMA1", -1) < 0 && blocks(c->s1, c->d1, p, rp) < 256) {
-    c->d1 = dma_config(rp, true, true, c->bf16);
-    c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
-  }
-  if (env_int("NMF_DMA2", -1) < 0 && blocks(c->s2, c->d2, rp, n) < 256) {
-    c->d2 = dma_config(rp, false, true, c->bf16);
-    c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
-  }
+  if (blocks(c->s1, c->d1, p, rp) < 256) c->d1 = dma_config(rp, true, true, c->bf16);
+  if (blocks(c->s2, c->d2, rp, n) < 256) c->d2 = dma_config(rp, false, true, c->bf16);
+  const int64_t id1 = env_int("NMF_DMA1", -1), id2 = env_int("NMF_DMA2", -1);
+  if (id1 >= 0 && fits1(dma_config_by_id((int)id1))) c->d1 = dma_config_by_id((int)id1);
+  if (id2 >= 0 && fits2(dma_config_by_id((int)id2))) c->d2 = dma_config_by_id((int)id2);
+  if (!fits1(c->d1) || !fits2(c->d2)) return NMF_EUNSUPPORTED;
+  c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
+  c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
   c->fuse = rp <= 64;
   if (!c->fuse) {
     if (!c->bf16) {

@@ -345,6 +345,27 @@ def test_default_tiles_mid_size(gpu_lib, r, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_tile_override_that_does_not_fit_is_ignored(gpu_lib, monkeypatch, precision):
+    """A product tile must divide the padded row counts it copies.  Tile 15
+    is 256 rows tall; as the pass-2 tile at padded rank 128 it would read
+    past the 128 rows of W^T, so the override is ignored on the host and the
+    results equal the default tiling's bit for bit."""
+    V, W0, H0 = g.image_like(512, 1024, 100, seed=81, init_seed=82)
+    runs = []
+    for override in (None, "15"):
+        if override:
+            monkeypatch.setenv("NMF_DMA2", override)
+        else:
+            monkeypatch.delenv("NMF_DMA2", raising=False)
+        ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0, precision=precision)
+        ctx.step(3)
+        runs.append((host(Wd), host(Hd), ctx.objective()))
+        ctx.close()
+    (Wa, Ha, fa), (Wb, Hb, fb) = runs
+    assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb) and fa == fb
+
+
 # ------------------------------------------------------------------ BF16 tier
 # The BF16 tier rounds every product operand (V, W, H and the r x r Grams) to
 # bfloat16 (RNE) and accumulates in float32 with float32 master factors.  The
