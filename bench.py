@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--ws-train", type=int, default=800, help="training matrices")
     ap.add_argument("--ws-test", type=int, default=16, help="held-out matrices timed")
     ap.add_argument("--ws-epochs", type=int, default=6)
+    ap.add_argument("--ws-target-tol", type=float, default=1e-4,
+                    help="training targets: each training matrix solved to this gap (the "
+                         "solver-converged factors); <= 0 uses --ws-target-iters iterations")
     ap.add_argument("--ws-target-iters", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the FP64 oracle baseline sample (0 disables)")
@@ -331,7 +334,14 @@ def warm_start_experiment(args, log):
     Wbar = ws.mean_dictionary(train[:16], 48, iters=600, precision="bf16")
     t_dict = time.perf_counter() - t0
     t0 = time.perf_counter()
-    Hs = ws.fit_targets(train, Wbar, iters=args.ws_target_iters, precision="bf16")
+    Hs = []
+    for a in range(0, len(train), 100):
+        if args.ws_target_tol > 0:
+            Hs += ws.fit_targets(train[a:a + 100], Wbar, precision="bf16", tol=args.ws_target_tol)
+        else:
+            Hs += ws.fit_targets(train[a:a + 100], Wbar, iters=args.ws_target_iters,
+                                 precision="bf16")
+        log(f"targets {min(a + 100, len(train))}/{len(train)} at {time.perf_counter() - t0:.1f} s")
     t_targets = time.perf_counter() - t0
     t0 = time.perf_counter()
     net = ws.make_network(gen.mlp_init(1024, 512, 48, 5001), Hs, max_batch=512)
@@ -364,6 +374,10 @@ def warm_start_experiment(args, log):
                     "* LogNormal(0,0.1), H_m sparse Exp; rank 48; gap f/||V||^2 <= 1e-4, "
                     "objective checked every 10 iterations",
         "train_matrices": args.ws_train, "test_matrices": args.ws_test,
+        "targets": (f"H of each training matrix solved from (W-bar, constant H) to gap "
+                    f"{args.ws_target_tol:g}, BF16, unit-norm-column gauge"
+                    if args.ws_target_tol > 0 else
+                    f"H after {args.ws_target_iters} BF16 iterations from (W-bar, constant H)"),
         "network": "1024-512-48 relu/softplus, bf16 products, Adam",
         "median": med,
         "warm_start": "H0 = network(V); W0 = least-squares dictionary for H0, clipped to "

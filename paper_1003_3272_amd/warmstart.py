@@ -10,9 +10,10 @@ This module only schedules those calls and moves tensors between them.
 Pipeline (for a stream of matrices V_m that share a dictionary):
 1. mean dictionary W-bar: a joint factorization of the column-wise
    concatenation of a few training matrices, columns scaled to unit norm;
-2. targets: each training matrix is factored starting from W = W-bar, and
-   the result is put in the unit-norm-column gauge, so that its H columns h_j
-   are expressed in (nearly) W-bar's basis;
+2. targets: each training matrix is factored starting from W = W-bar (to
+   the same gap tolerance the solves use, or for a fixed iteration count),
+   and the result is put in the unit-norm-column gauge, so that its H
+   columns h_j are expressed in (nearly) W-bar's basis;
 3. the network is trained on the pairs (v_j, h_j);
 4. a new matrix starts from H0 = network(V) and W0 = W-bar ("net"), or W0 =
    the least-squares dictionary for H0 clipped to a positive floor
@@ -47,17 +48,25 @@ def mean_dictionary(Vs, r, iters, precision="bf16", seed=1):
     return W
 
 
-def fit_targets(Vs, Wbar, iters, precision="bf16"):
-    """For each V: factor from (W-bar, constant H) for `iters` iterations and
-    return H in the unit-norm-column gauge (r x n tensors)."""
+def fit_targets(Vs, Wbar, iters=None, precision="bf16", tol=None, check_every=50,
+                max_iters=20000):
+    """For each V: factor from (W-bar, constant H) and return H in the
+    unit-norm-column gauge (r x n tensors).  With tol: run to the gap
+    f / ||V||^2 <= tol (the solver-converged factors); else `iters`
+    iterations."""
     import torch
     out = []
     r = Wbar.shape[1]
     for V in Vs:
         W = Wbar.clone()
         H = torch.full((r, V.shape[1]), 1.0 / r, dtype=torch.float32, device=V.device)
-        with nmf.Nmf(V, W, H, precision=precision) as ctx:
-            ctx.step(iters)
+        if tol is not None:
+            with nmf.Nmf(V, W, H, precision=precision, tol_kind="gap", tol=tol,
+                         check_every=check_every) as ctx:
+                ctx.solve(max_iters)
+        else:
+            with nmf.Nmf(V, W, H, precision=precision) as ctx:
+                ctx.step(iters)
         nmf.normalize_gauge(W, H)
         out.append(H)
     _sync()
