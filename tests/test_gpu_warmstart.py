@@ -1,6 +1,7 @@
 """Warm-start pipeline on a small stream of matrices sharing a dictionary:
-the trained network's start reaches the objective gap in fewer iterations
-than a cold start, and every run still reaches the tolerance."""
+the network, trained on solver-converged targets, gives starts that reach
+the objective gap in fewer iterations than a cold start and than W-bar with
+a constant H, and every run still reaches the tolerance."""
 import numpy as np
 import pytest
 import torch
@@ -19,27 +20,41 @@ def test_warm_start_pipeline_small(gpu_lib):
     Wbar = ws.mean_dictionary(train[:8], r, iters=400)
     norms = torch.linalg.vector_norm(Wbar, dim=0).cpu().numpy()
     assert np.allclose(norms, 1.0, atol=1e-5)
+    # training on targets after 200 iterations: the float64 oracle with bf16
+    # products, run through the same schedule, goes from about 3e-2 to 2e-3
+    # (a constant predictor scores 8.5e-2)
     Hs = ws.fit_targets(train, Wbar, iters=200)
     net = ws.make_network(g.mlp_init(p, 128, r, 5), Hs, max_batch=128)
     losses = ws.train(net, train, Hs, epochs=12, lr=1e-3, batch=128)
-    # the float64 oracle with bf16 products, run through the same schedule,
-    # goes from about 3e-2 to 2e-3 (a constant predictor scores 8.5e-2)
     print("training loss per epoch:", ["%.3e" % x for x in losses])
     assert losses[-1] < 0.2 * losses[0] and losses[-1] < 1e-2
-    res = {k: [] for k in ("cold", "wbar", "net", "net_ls")}
+    net.close()
+    # the pipeline's network: targets solved to the gap the test uses
+    TOL = 3e-4
+    Hs = ws.fit_targets(train, Wbar, tol=TOL)
+    net = ws.make_network(g.mlp_init(p, 128, r, 5), Hs, max_batch=128)
+    ws.train(net, train, Hs, epochs=12, lr=1e-3, batch=128)
+    res = {k: [] for k in ("cold", "wbar", "net", "hfit_ls", "net_ls")}
+    kw = dict(tol=TOL, check_every=1)  # every iteration counted
     for i, V in enumerate(test):
-        res["cold"].append(ws.solve_to_gap(V, "cold", tol=2e-3, precision="fp32", seed=9000 + i,
-                                           Wbar=Wbar))
-        res["wbar"].append(ws.solve_to_gap(V, "wbar", tol=2e-3, precision="bf16", Wbar=Wbar))
-        res["net"].append(ws.solve_to_gap(V, "net", tol=2e-3, precision="bf16", Wbar=Wbar,
-                                          net=net))
-        res["net_ls"].append(ws.solve_to_gap(V, "net_ls", tol=2e-3, precision="bf16",
-                                             Wbar=Wbar, net=net))
+        res["cold"].append(ws.solve_to_gap(V, "cold", precision="fp32", seed=9000 + i,
+                                           Wbar=Wbar, **kw))
+        res["wbar"].append(ws.solve_to_gap(V, "wbar", precision="bf16", Wbar=Wbar, **kw))
+        res["net"].append(ws.solve_to_gap(V, "net", precision="bf16", Wbar=Wbar, net=net, **kw))
+        res["hfit_ls"].append(ws.solve_to_gap(V, "hfit_ls", precision="bf16", Wbar=Wbar, **kw))
+        res["net_ls"].append(ws.solve_to_gap(V, "net_ls", precision="bf16", Wbar=Wbar, net=net,
+                                             **kw))
     for k, v in res.items():
-        assert all(x["converged"] and x["gap"] <= 2e-3 for x in v), (k, v)
+        assert all(x["converged"] and x["gap"] <= TOL for x in v), (k, v)
     it = {k: np.median([x["iters"] for x in v]) for k, v in res.items()}
-    print("median iterations to gap 2e-3:", it)
+    print(f"median iterations to gap {TOL:g}:", it, flush=True)
     assert it["net"] < it["cold"]
+    # what the network adds: from W-bar, its H0 against a constant H (about
+    # 59 against 155 iterations here).  With the least-squares W0 the two
+    # starts are level at this size (the refit alone lands close on these
+    # small rank-8 problems); at 1024 x 4096 the bench measures 135 against
+    # 3045 iterations for that pair.
+    assert it["net"] < 0.7 * it["wbar"]
     net.close()
 
 
