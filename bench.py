@@ -349,6 +349,10 @@ def warm_start_experiment(args, log):
                       log=log)
     t_train = time.perf_counter() - t0
     del Hs
+    # inference copy sized for a whole test matrix (one pass, no chunks)
+    infer = ws.inference_copy(net, max(V.shape[1] for V in test))
+    net.close()
+    net = infer
     runs = {"fp32_cold": [], "bf16_cold": [], "bf16_wbar": [], "bf16_net": [],
             "bf16_hfit_ls": [], "bf16_net_ls": []}
     for i, V in enumerate(test):

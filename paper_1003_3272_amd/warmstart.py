@@ -94,6 +94,13 @@ def make_network(params, Hs, max_batch):
     return nmf.Mlp([M1, b1, M2, b2], max_batch=max_batch)
 
 
+def inference_copy(net, max_batch):
+    """A copy of a trained network whose buffers take max_batch columns at
+    once, so a whole matrix is predicted in one pass instead of in chunks of
+    the training batch."""
+    return nmf.Mlp(net.params(), max_batch=max_batch)
+
+
 def train(net, Vs, Hs, epochs, lr, batch=512, decay=0.9, seed=0, log=None):
     """Adam epochs over the (V_m, H_m) pairs in minibatches of `batch`
     columns (column slices, no copies); matrices in a seeded random order

@@ -55,6 +55,12 @@ def test_warm_start_pipeline_small(gpu_lib):
     # small rank-8 problems); at 1024 x 4096 the bench measures 135 against
     # 3045 iterations for that pair.
     assert it["net"] < 0.7 * it["wbar"]
+    # the inference copy (whole matrix in one pass) predicts the same H0 up
+    # to float32 summation order
+    infer = ws.inference_copy(net, n)
+    h_chunks, h_whole = net.predict(test[0]), infer.predict(test[0])
+    assert torch.allclose(h_whole, h_chunks, rtol=1e-4, atol=1e-6)
+    infer.close()
     net.close()
 
 
