@@ -366,6 +366,28 @@ def test_tile_override_that_does_not_fit_is_ignored(gpu_lib, monkeypatch, precis
     assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb) and fa == fb
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("r", [32, 256])
+def test_precision_tier_full_size_one_iteration(gpu_lib, r):
+    """8192 x 32768 (the precision tier's size) at ranks 32 (split-K passes,
+    fused Grams) and 256 (single-tile passes, separate Gram products and the
+    matrix-core update epilogues): one FP32 iteration against the float64
+    oracle in full."""
+    V, W0, H0 = g.precision_tier(r)
+    ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0)
+    fs = [ctx.objective()]
+    ctx.step(1)
+    fs.append(ctx.objective())
+    W1, H1 = host(Wd), host(Hd)
+    ctx.close()
+    del Vd, Wd, Hd
+    torch.cuda.empty_cache()
+    Wo, Ho, tr = o.run(V, W0, H0, 1)
+    assert np.max(np.abs(np.array(fs) - tr) / tr) < 1e-5, (fs, tr)
+    assert frob_rel(W1, Wo) < 1e-4
+    assert frob_rel(H1, Ho) < 1e-4
+
+
 # ------------------------------------------------------------------ BF16 tier
 # The BF16 tier rounds every product operand (V, W, H and the r x r Grams) to
 # bfloat16 (RNE) and accumulates in float32 with float32 master factors.  The
@@ -391,6 +413,27 @@ def test_bf16_half_steps_vs_emulated_oracle(gpu_lib, p, n, r):
         Href = o.update_h(V, Win, Hin, bf16=True)
         err = np.abs(host(Hd) - Href) / Href
         assert err.max() < 2e-3 and np.median(err) < 1e-5, (err.max(), np.median(err))
+    ctx.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("r", [32, 256])
+def test_bf16_half_steps_full_size(gpu_lib, r):
+    """8192 x 32768 at ranks 32 and 256, BF16 tier: one W and one H
+    half-step against the oracle's bf16-emulated half-steps from the GPU's
+    own input state, to the bar of the small cases."""
+    V, W0, H0 = g.precision_tier(r)
+    V = V + np.float32(1e-3)  # no exact zeros in the factors (relative errors)
+    ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0, precision="bf16")
+    Win, Hin = host(Wd), host(Hd)
+    ctx.update_w()
+    Wg = host(Wd)
+    err = np.abs(Wg - o.update_w(V, Win, Hin, bf16=True)) / Wg
+    assert err.max() < 2e-3 and np.median(err) < 1e-5, (err.max(), np.median(err))
+    ctx.update_h()
+    Hg = host(Hd)
+    err = np.abs(Hg - o.update_h(V, Wg, Hin, bf16=True)) / Hg
+    assert err.max() < 2e-3 and np.median(err) < 1e-5, (err.max(), np.median(err))
     ctx.close()
 
 
