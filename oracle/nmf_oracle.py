@@ -20,7 +20,7 @@ Every array is promoted to float64 on entry; nothing is blocked, fused or
 reordered beyond the definitions cited at each function.  Matrix products use
 numpy's matmul (a library primitive).
 
-Readings of points the paper leaves open (all listed in the design doc):
+Readings of points the paper leaves open:
   * denominators use the Gram association W (H H^T) and (W^T W) H, which is
     algebraically the paper's V_n W_n W_n^t and V_{n+1}^t V_{n+1} W_n;
   * a zero (or non-positive) denominator keeps the entry unchanged, a valid
