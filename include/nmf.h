@@ -104,9 +104,11 @@ nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n,
 /* Enqueue `iters` (>= 0) full iterations of Algorithm 1 (NNMF): the W
    update of eq. nnmf_v_update followed by the H update of eq.
    nnmf_w_update with the new W.  Asynchronous; no host synchronization.
-   With use_graph the iterations are replayed from HIP graphs captured on
-   first use (while the profiler is running, kernels are launched directly
-   so that every stage can be timed). */
+   With use_graph the iterations are replayed from HIP graphs of 16, 8, 4,
+   2 and 1 iterations, each captured on first use (iters = 16 q + the
+   binary digits of the rest: at most q + 4 replays); while the profiler is
+   running, kernels are launched directly so that every stage can be
+   timed. */
 nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
 
 /* Enqueue only the W half-step (eq. nnmf_v_update):
