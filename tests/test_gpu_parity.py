@@ -81,6 +81,8 @@ SHAPES = [
     (260, 520, 200),    # rank padded to 256
     (1, 5, 1),          # degenerate: one row, rank 1
     (640, 2, 2),        # two columns
+    (12, 10, 20),       # rank above both dimensions
+    (3, 300, 7),        # rank above p
 ]
 
 
