@@ -369,12 +369,12 @@ def test_tile_override_that_does_not_fit_is_ignored(gpu_lib, monkeypatch, precis
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("r", [32, 256])
+@pytest.mark.parametrize("r", [32, 128, 256])
 def test_precision_tier_full_size_one_iteration(gpu_lib, r):
     """8192 x 32768 (the precision tier's size) at ranks 32 (split-K passes,
-    fused Grams) and 256 (single-tile passes, separate Gram products and the
-    matrix-core update epilogues): one FP32 iteration against the float64
-    oracle in full."""
+    fused Grams), 128 (separate Gram products, float32 W update, matrix-core
+    H update) and 256 (single-tile passes, both updates on the matrix
+    cores): one FP32 iteration against the float64 oracle in full."""
     V, W0, H0 = g.precision_tier(r)
     ctx, Vd, Wd, Hd = make(gpu_lib, V, W0, H0)
     fs = [ctx.objective()]
@@ -419,9 +419,9 @@ def test_bf16_half_steps_vs_emulated_oracle(gpu_lib, p, n, r):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("r", [32, 256])
+@pytest.mark.parametrize("r", [32, 128, 256])
 def test_bf16_half_steps_full_size(gpu_lib, r):
-    """8192 x 32768 at ranks 32 and 256, BF16 tier: one W and one H
+    """8192 x 32768 at ranks 32, 128 and 256, BF16 tier: one W and one H
     half-step against the oracle's bf16-emulated half-steps from the GPU's
     own input state, to the bar of the small cases."""
     V, W0, H0 = g.precision_tier(r)
