@@ -1212,6 +1212,19 @@ __device__ __forceinline__ void stage_put(char* lds, int t, int e, float v) {
   }
 }
 
+// elements e4 .. e4 + 3 (e4 a multiple of 4) of staged row t in one store:
+// 16 bytes (float32) or 8 bytes (bfloat16), at the offsets of stage_off
+template <bool BF>
+__device__ __forceinline__ void stage_put4(char* lds, int t, int e4, float4 v) {
+  if constexpr (BF) {
+    const uint2 h = make_uint2((uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16),
+                               (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16));
+    *reinterpret_cast<uint2*>(lds + stage_off<2>(t, e4)) = h;
+  } else {
+    *reinterpret_cast<float4*>(lds + stage_off<4>(t, e4)) = v;
+  }
+}
+
 // acc[i][j] += A rows (a0 + 16 i + c) x B^T rows (b0 + 16 j + c) over one
 // staged chunk (KE = 128 / ES elements of K).
 template <int MI, int NJ, bool BF>
@@ -1277,20 +1290,13 @@ __global__ __launch_bounds__(256 * WR) void k_update_w_mma(
       // A: rows i0 .. i0 + ROWS of W (ppad rows, zero beyond p), columns l0 ..
       for (int idx = tid; idx < ROWS * KE / 4; idx += T) {
         const int t = idx / (KE / 4), e4 = 4 * (idx % (KE / 4));
-        const float4 w = *reinterpret_cast<const float4*>(&Wp[(i0 + t) * RP + l0 + e4]);
-        stage_put<BF>(As, t, e4 + 0, w.x);
-        stage_put<BF>(As, t, e4 + 1, w.y);
-        stage_put<BF>(As, t, e4 + 2, w.z);
-        stage_put<BF>(As, t, e4 + 3, w.w);
+        stage_put4<BF>(As, t, e4, *reinterpret_cast<const float4*>(&Wp[(i0 + t) * RP + l0 + e4]));
       }
-      // B^T: row k holds G[l0 .. l0 + KE][k]
-      for (int idx = tid; idx < KE * RP / 4; idx += T) {
-        const int e = idx / (RP / 4), k4 = 4 * (idx % (RP / 4));
-        const float4 gv = *reinterpret_cast<const float4*>(&G[(int64_t)(l0 + e) * RP + k4]);
-        stage_put<BF>(Bs, k4 + 0, e, gv.x);
-        stage_put<BF>(Bs, k4 + 1, e, gv.y);
-        stage_put<BF>(Bs, k4 + 2, e, gv.z);
-        stage_put<BF>(Bs, k4 + 3, e, gv.w);
+      // B^T: row k holds G[l0 .. l0 + KE][k], which is row k of G (a Gram
+      // matrix is symmetric), so it is staged like A
+      for (int idx = tid; idx < RP * KE / 4; idx += T) {
+        const int t = idx / (KE / 4), e4 = 4 * (idx % (KE / 4));
+        stage_put4<BF>(Bs, t, e4, *reinterpret_cast<const float4*>(&G[(int64_t)t * RP + l0 + e4]));
       }
       __syncthreads();
       mma_chunk<MI, NJ, BF>(As, ib, Bs, kb, acc);
@@ -1390,11 +1396,7 @@ __global__ __launch_bounds__(256 * WC) void k_update_h_mma(
       // A: rows of G, columns l0 ..
       for (int idx = tid; idx < RP * KE / 4; idx += T) {
         const int t = idx / (KE / 4), e4 = 4 * (idx % (KE / 4));
-        const float4 gv = *reinterpret_cast<const float4*>(&G[(int64_t)t * RP + l0 + e4]);
-        stage_put<BF>(As, t, e4 + 0, gv.x);
-        stage_put<BF>(As, t, e4 + 1, gv.y);
-        stage_put<BF>(As, t, e4 + 2, gv.z);
-        stage_put<BF>(As, t, e4 + 3, gv.w);
+        stage_put4<BF>(As, t, e4, *reinterpret_cast<const float4*>(&G[(int64_t)t * RP + l0 + e4]));
       }
       // B^T: row jj holds H[l0 .. l0 + KE][j0 + jj] (H is rp x ldh, zero-padded)
       for (int idx = tid; idx < KE * COLS / 4; idx += T) {
