@@ -9,12 +9,17 @@ resident in HBM.  Objective evaluations are not part of a step (fixed-count
 iterations, as the paper times its GPU runs); the objective is evaluated
 once after the timed region as a sanity check.
 
-Prints one JSON line: iterations/s, the roofline of the dominant kernel
-(from HIP events recorded around every stage inside the timed region) and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: iterations/s of the default path (the iterations
+replayed from HIP graphs, no profiler), the roofline of the dominant kernel
+(its mean duration from HIP events recorded around every stage in a second
+window of the same number of iterations, launched directly) and the FP64
+CPU oracle timed on a bounded sample of the same workload, on one host core
+and on all of them.
 
 Then (unless --no-stream-reference) a plain 1.07 GB device copy by torch, as
 a practical HBM streaming rate beside the 8000 GB/s peak.
+Then (unless --no-rank-sweep) the same shape at ranks 8, 16, 32 and 64 in
+both tiers (the HBM-bound regime of the FP32 tier is rank <= 39).
 Then (unless --no-precision-tier) the FP32 and BF16 tiers at 8192 x 32768
 for ranks 32, 128 and 256, then (unless --no-batch) the batched tier: 512 problems of uneven shape,
 200 iterations each in one persistent launch, against a loop of the
@@ -31,6 +36,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -58,6 +65,10 @@ def parse():
                     help="skip the reference copy that measures a practical HBM rate")
     ap.add_argument("--no-precision-tier", action="store_true",
                     help="skip the 8192 x 32768 FP32 / BF16 rank sweep")
+    ap.add_argument("--no-rank-sweep", action="store_true",
+                    help="skip the rank sweep {8, 16, 32, 64} at the headline shape")
+    ap.add_argument("--sweep-ranks", type=int, nargs="+", default=[8, 16, 32, 64])
+    ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--pt-iters", type=int, default=200)
     ap.add_argument("--pt-ranks", type=int, nargs="+", default=[32, 128, 256])
     ap.add_argument("--pmc-calibration", action="store_true",
@@ -67,37 +78,93 @@ def parse():
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the time-to-tolerance experiment")
     ap.add_argument("--ws-train", type=int, default=800, help="training matrices")
-    ap.add_argument("--ws-test", type=int, default=16, help="held-out matrices timed")
+    ap.add_argument("--ws-test", type=int, default=64, help="held-out matrices timed")
     ap.add_argument("--ws-epochs", type=int, default=6)
     ap.add_argument("--ws-target-tol", type=float, default=1e-4,
                     help="training targets: each training matrix solved to this gap (the "
                          "solver-converged factors); <= 0 uses --ws-target-iters iterations")
     ap.add_argument("--ws-target-iters", type=int, default=200)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="budget of the FP64 oracle baseline sample (0 disables)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="budget of each FP64 oracle baseline leg (0 disables)")
+    ap.add_argument("--cpu-gap-seconds", type=float, default=60.0,
+                    help="cap of the oracle's time to the 1e-4 gap on one warm-start "
+                         "matrix (0 disables)")
     return ap.parse_args()
 
 
-def cpu_baseline(V, W0, H0, seconds):
-    """FP64 oracle iterations on the host cores, bounded to about `seconds`."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+def host_cpu():
+    """Model name and logical core count of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "cpu_count": os.cpu_count()}
 
+
+def _oracle_rate(V64, W0, H0, seconds, max_iters=1000):
+    """FP64 oracle iterations per second from (W0, H0), bounded to about
+    `seconds` (at least one iteration)."""
     from oracle import nmf_oracle as oracle
-    V64 = V.astype(np.float64)
     W, H = W0.astype(np.float64), H0.astype(np.float64)
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     t0 = time.perf_counter()
     k = 0
     while True:
         W, H = oracle.step(V64, W, H)
         k += 1
         el = time.perf_counter() - t0
-        if el >= seconds or k >= 1000:
-            break
-    return {"value": k / el, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{k} FP64 iterations (numpy BLAS) of the same workload from the same "
-                      f"start, {el:.1f} s"}
+        if el >= seconds or k >= max_iters:
+            return k, el
+
+
+def cpu_baseline(V, W0, H0, seconds):
+    """The FP64 oracle (numpy BLAS) on the host: iterations/s on all host
+    cores (the reported value) and on one core (the paper's CPU baseline ran
+    on one core, Sec. 3), each leg bounded to about `seconds`."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    V64 = V.astype(np.float64)
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    k_all, el_all = _oracle_rate(V64, W0, H0, seconds)
+    with threadpool_limits(1):
+        k_one, el_one = _oracle_rate(V64, W0, H0, seconds)
+    return {"value": k_all / el_all, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{k_all} FP64 iterations (numpy BLAS, {threads} threads) of the same "
+                      f"workload from the same start, {el_all:.1f} s",
+            "one_core": {"value": k_one / el_one, "unit": "iters/s", "cores": 1,
+                         "sample": f"{k_one} FP64 iterations on one thread, {el_one:.1f} s"},
+            "host": host_cpu()}
+
+
+def oracle_time_to_gap(V, m, cap_s, tol=1e-4, check_every=10):
+    """The FP64 oracle's wall time to f / ||V||^2 <= tol on one warm-start
+    matrix from a U(0,1) start (numpy PCG64, seed 400000 + m), objective
+    checked every `check_every` iterations, all host cores; stops at cap_s
+    seconds (then reports the gap reached)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import nmf_oracle as oracle
+    from synth import generators as gen
+    p, n = V.shape
+    V64 = V.astype(np.float64)
+    W0, H0 = gen.uniform_init(p, n, 48, seed=400000 + m)
+    W, H = W0.astype(np.float64), H0.astype(np.float64)
+    nv2 = float(np.sum(V64 * V64))
+    t0 = time.perf_counter()
+    k = 0
+    gap = oracle.objective(V64, W, H) / nv2
+    while gap > tol and time.perf_counter() - t0 < cap_s:
+        for _ in range(check_every):
+            W, H = oracle.step(V64, W, H)
+        k += check_every
+        gap = oracle.objective(V64, W, H) / nv2
+    el = time.perf_counter() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    return {"matrix": m, "seconds": round(el, 2), "iters": k, "gap": gap,
+            "converged": bool(gap <= tol), "threads": int(threads), "check_every": check_every,
+            "start": "U(0,1) numpy PCG64 seed 400000+m (the GPU cold starts draw on the device)"}
 
 
 def _gen_matrix(args):
@@ -162,18 +229,135 @@ def _precision_case(r):
     return gen.precision_tier(r)
 
 
+def timed_steps(ctx, steps):
+    """Seconds for `steps` iterations on the default path (iterations
+    replayed from the HIP graphs captured beforehand, profiler off),
+    synchronized on both sides."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def profiled_steps(ctx, steps):
+    """{stage: (total ms, launches)} of `steps` iterations launched directly
+    with HIP events recorded around every stage on the context's stream."""
+    ctx.profile_start(8 * steps)
+    ctx.step(steps)
+    return ctx.profile_stop()
+
+
+def pass_roofline(stages, p, n, r, prec):
+    """Roofline of the slower V-streaming pass: 2 p n r flops and p n s_V
+    bytes of V per launch (s_V = 4 for FP32, 2 for BF16), against whichever
+    of the two peaks binds."""
+    passes = {k: stages[k][0] / max(1, stages[k][1]) for k in ("gemm_vht", "gemm_wtv")}
+    dom = max(passes, key=passes.get)
+    ms = passes[dom]
+    flops = 2.0 * p * n * r
+    vbytes = p * n * (4 if prec == "fp32" else 2)
+    peak_t = PEAK_TFLOPS[prec]
+    if flops / (peak_t * 1e12) >= vbytes / (PEAK_HBM_GBS * 1e9):
+        ach = flops / (ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_t, "unit": "TFLOP/s"}
+    else:
+        ach = vbytes / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["kernel"] = dom
+    roof["kernel_ms"] = round(ms, 4)
+    roof["v_pass_gbs"] = round(vbytes / (ms * 1e-3) / 1e9, 1)
+    roof["other_pass_ms"] = round(passes["gemm_wtv" if dom == "gemm_vht" else "gemm_vht"], 4)
+    return roof
+
+
+def rank_sweep(Vd, args, log):
+    """The headline matrix at factorization ranks 8, 16, 32 and 64, both
+    tiers: iterations/s on the default path and the roofline of the slower
+    pass (HBM-bound in FP32 below rank 39, in BF16 throughout)."""
+    import torch
+
+    from paper_1003_3272_amd import nmf
+    from synth import generators as gen
+    p, n = Vd.shape
+    out = {"workload": f"the headline V ({p}x{n}, planted rank {args.r}), factorization rank r, "
+                       f"U(0,1) start seed 2002", "steps": args.sweep_steps, "ranks": {}}
+    for r in args.sweep_ranks:
+        W0, H0 = gen.uniform_init(p, n, r, seed=2002)
+        res = {}
+        for prec in ("fp32", "bf16"):
+            Wd, Hd = torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda()
+            with nmf.Nmf(Vd, Wd, Hd, precision=prec) as ctx:
+                ctx.prepare_graphs()
+                ctx.step(4)
+                el = timed_steps(ctx, args.sweep_steps)
+                st = profiled_steps(ctx, min(args.sweep_steps, 50))
+            res[prec] = {"iters_per_s": round(args.sweep_steps / el, 1),
+                         "roofline": pass_roofline(st, p, n, r, prec)}
+            del Wd, Hd
+        out["ranks"][str(r)] = res
+        log(f"rank sweep r={r}: fp32 {res['fp32']['iters_per_s']} it/s "
+            f"({res['fp32']['roofline']['bound']} {res['fp32']['roofline']['frac']}), bf16 "
+            f"{res['bf16']['iters_per_s']} it/s ({res['bf16']['roofline']['bound']} "
+            f"{res['bf16']['roofline']['frac']})")
+    return out
+
+
+def _fp64_reference():
+    """The float64 oracle's 200-iteration trajectory of the precision-tier
+    workload, stored by tests/golden/make_precision_tier_fp64.py (None if
+    the file is absent)."""
+    path = os.path.join(ROOT, "tests", "golden", "precision_tier_fp64.json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def _sample_positions(rows, cols, count, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, rows, size=count), rng.integers(0, cols, size=count)
+
+
+def err_vs_fp64(ref, r, f, W, H):
+    """Errors of a 200-iteration GPU result against the float64 oracle's:
+    objective, Frobenius norms of W and H, and the largest relative error
+    over the stored sample of entries of W and H (entries above 1e-6 of the
+    sample's largest)."""
+    rr = ref["ranks"].get(str(r)) if ref else None
+    if rr is None:
+        return None
+    cnt, seed = ref["sample"]["count"], ref["sample"]["seed"]
+    wi, wk = _sample_positions(rr["p"], r, cnt, seed)
+    hk, hj = _sample_positions(r, rr["n"], cnt, seed)
+
+    def worst(got, want):
+        want = np.asarray(want)
+        keep = np.abs(want) > 1e-6 * np.abs(want).max()
+        return float(np.max(np.abs(got[keep] - want[keep]) / np.abs(want[keep])))
+
+    f64 = rr["f"]["200"]
+    return {"f200_fp64": f64, "f200_rel": abs(f - f64) / f64,
+            "normW_rel": abs(float(np.linalg.norm(W)) - rr["norm_W"]["200"]) / rr["norm_W"]["200"],
+            "normH_rel": abs(float(np.linalg.norm(H)) - rr["norm_H"]["200"]) / rr["norm_H"]["200"],
+            "W_sample_max_rel": worst(W[wi, wk], rr["W200_sample"]),
+            "H_sample_max_rel": worst(H[hk, hj], rr["H200_sample"])}
+
+
 def precision_tier_experiment(args, log):
-    """8192 x 32768, planted rank r in {32, 128, 256}: iterations/s of the
-    FP32 and BF16 tiers over 200 iterations from the same start, each pass's
-    roofline, and the BF16 objective relative to FP32 (which matches the
-    float64 oracle to 1e-5 by the parity tests)."""
-    import numpy as np
+    """8192 x 32768, planted rank r in {32, 128, 256}: exactly 200
+    iterations of each tier from the same start on the default path (their
+    time gives iterations/s), the result's error against the float64
+    oracle's 200-iteration trajectory, then a profiled window for each
+    pass's roofline."""
     import torch
 
     from paper_1003_3272_amd import nmf
 
+    ref = _fp64_reference()
     out = {"workload": "8192x32768 image-like V (Gamma(2,0.5) x sparse Exp, rescaled), seed "
-                       "1003+r, U(0,1) start seed 2003+r", "iterations": args.pt_iters, "ranks": {}}
+                       "1003+r, U(0,1) start seed 2003+r", "iterations": args.pt_iters,
+           "fp64_reference": "tests/golden/precision_tier_fp64.json (float64 oracle, 200 "
+                             "iterations)" if ref else None, "ranks": {}}
     for r in args.pt_ranks:
         t0 = time.perf_counter()
         V, W0, H0 = _precision_case(r)
@@ -184,38 +368,27 @@ def precision_tier_experiment(args, log):
         for prec in ("fp32", "bf16"):
             Wd, Hd = torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda()
             with nmf.Nmf(Vd, Wd, Hd, precision=prec) as ctx:
-                ctx.step(2)
-                torch.cuda.synchronize()
-                ctx.profile_start(8 * args.pt_iters)
-                t0 = time.perf_counter()
-                ctx.step(args.pt_iters - 2)
-                torch.cuda.synchronize()
-                el = time.perf_counter() - t0
-                st = ctx.profile_stop()
+                ctx.prepare_graphs()
+                el = timed_steps(ctx, args.pt_iters)
                 f = ctx.objective()
                 nv2 = ctx.data_norm2()
+                W, H = Wd.cpu().numpy(), Hd.cpu().numpy()
+                st = profiled_steps(ctx, 20)
             p_, n_ = Vd.shape
-            passes = {k: st[k][0] / max(1, st[k][1]) for k in ("gemm_vht", "gemm_wtv")}
-            dom = max(passes, key=passes.get)
-            flops = 2.0 * p_ * n_ * r
-            vbytes = p_ * n_ * (4 if prec == "fp32" else 2)
-            tf = flops / (passes[dom] * 1e-3) / 1e12
-            gbs = vbytes / (passes[dom] * 1e-3) / 1e9
-            if flops / (PEAK_TFLOPS[prec] * 1e12) >= vbytes / (PEAK_HBM_GBS * 1e9):
-                roof = {"bound": "mfma", "frac": round(tf / PEAK_TFLOPS[prec], 4)}
-            else:
-                roof = {"bound": "hbm", "frac": round(gbs / PEAK_HBM_GBS, 4)}
-            res[prec] = {"iters_per_s": round((args.pt_iters - 2) / el, 1),
-                         "pass_ms": round(passes[dom], 4), "tflops": round(tf, 1),
-                         "v_pass_gbs": round(gbs, 1), "roofline": roof,
+            res[prec] = {"iters_per_s": round(args.pt_iters / el, 1),
+                         "roofline": pass_roofline(st, p_, n_, r, prec),
                          "objective": f, "gap": f / nv2}
-            del Wd, Hd
+            if args.pt_iters == 200:
+                res[prec]["err_vs_fp64"] = err_vs_fp64(ref, r, f, W, H)
+            del Wd, Hd, W, H
         res["bf16_rel_objective_vs_fp32"] = abs(res["bf16"]["objective"] - res["fp32"]["objective"]) \
             / res["fp32"]["objective"]
         res["bf16_speedup"] = round(res["bf16"]["iters_per_s"] / res["fp32"]["iters_per_s"], 2)
         out["ranks"][str(r)] = res
-        log(f"precision tier r={r}: fp32 {res['fp32']['iters_per_s']} it/s, bf16 "
-            f"{res['bf16']['iters_per_s']} it/s, rel f {res['bf16_rel_objective_vs_fp32']:.2e}")
+        e32 = (res["fp32"].get("err_vs_fp64") or {}).get("f200_rel", float("nan"))
+        e16 = (res["bf16"].get("err_vs_fp64") or {}).get("f200_rel", float("nan"))
+        log(f"precision tier r={r}: fp32 {res['fp32']['iters_per_s']} it/s (f200 vs fp64 "
+            f"{e32:.2e}), bf16 {res['bf16']['iters_per_s']} it/s (f200 vs fp64 {e16:.2e})")
         del Vd
         torch.cuda.empty_cache()
     return out
@@ -345,6 +518,7 @@ def warm_start_experiment(args, log):
     t_targets = time.perf_counter() - t0
     t0 = time.perf_counter()
     net = ws.make_network(gen.mlp_init(1024, 512, 48, 5001), Hs, max_batch=512)
+    net.set_dictionary(Wbar)
     losses = ws.train(net, train, Hs, epochs=args.ws_epochs, lr=1e-3, batch=512, decay=0.8,
                       log=log)
     t_train = time.perf_counter() - t0
@@ -406,12 +580,12 @@ def main():
               "column-sharded design is described but not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1003_3272_amd import nmf
     from synth import generators as gen
 
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
     p, n, r = args.p, args.n, args.r
     V, _, _ = gen.sparse_planted(p, n, r, seed=1002)
     W0, H0 = gen.uniform_init(p, n, r, seed=2002)
@@ -423,7 +597,6 @@ def main():
         Vd = torch.from_numpy(V).to(dev)
     Wd = torch.from_numpy(W0).to(dev)
     Hd = torch.from_numpy(H0).to(dev)
-    stream = torch.cuda.current_stream()
 
     if args.pmc_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -434,43 +607,25 @@ def main():
         del src, dst
     ctx = nmf.Nmf(Vd, Wd, Hd, precision=args.precision)
     f0 = ctx.objective()
+    ctx.prepare_graphs()          # graph capture stays out of the timed region
     ctx.step(args.warmup)
-    torch.cuda.synchronize()
-
-    ctx.profile_start(8 * args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = ctx.profile_stop()
+    # timed region: exactly `steps` iterations on the default path
+    elapsed = timed_steps(ctx, args.steps)
     f_end = ctx.objective()
+    # second window, same length: per-stage HIP events (direct launches)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    stages = profiled_steps(ctx, args.steps)
+    elapsed_prof = time.perf_counter() - tp
     ctx.close()
 
     iters_per_s = args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-
-    # dominant kernel: the larger of the two V-streaming products
-    dom = max(("gemm_vht", "gemm_wtv"), key=lambda k: stages[k][0])
-    dom_ms = stages[dom][0] / max(1, stages[dom][1])
-    flops = 2.0 * p * n * r                       # 2r flops per entry of V
-    vbytes = p * n * (4 if args.precision == "fp32" else 2)
-    peak_t = PEAK_TFLOPS[args.precision]
-    t_comp = flops / (peak_t * 1e12)
-    t_mem = vbytes / (PEAK_HBM_GBS * 1e9)
-    if t_comp >= t_mem:
-        achieved = flops / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak_t,
-                "unit": "TFLOP/s"}
-    else:
-        achieved = vbytes / (dom_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s"}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = measured_traffic(dom, p, n, r, args.precision)
-    roof["kernel"] = dom
-    roof["kernel_ms"] = round(dom_ms, 4)
-    roof["v_pass_gbs"] = round(vbytes / (dom_ms * 1e-3) / 1e9, 1)
+    roof = pass_roofline(stages, p, n, r, args.precision)
+    roof["traffic"] = measured_traffic(roof["kernel"], p, n, r, args.precision)
+    roof["timing"] = ("kernel_ms: mean HIP-event duration of the launches of that pass in a "
+                      "second window of the same number of iterations, launched directly with "
+                      "events around every stage on the library's stream")
 
     out = {
         "metric": METRIC,
@@ -489,30 +644,36 @@ def main():
             "workload": f"image-like V {p}x{n} fp32 (Gamma(2,0.5) x sparse Exp, rescaled "
                         f"to [0,1]), rank {r}, U(0,1) init, {args.precision} products",
             "p": p, "n": n, "r": r, "precision": args.precision,
+            "path": "default: iterations replayed from HIP graphs, profiler off",
         },
         "roofline": roof,
         "stages_ms_per_iter": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items()
                                if v[1] > 0},
+        "profiled_window_ms_per_step": round(1e3 * elapsed_prof / args.steps, 4),
         "objective": {"f0": f0, "f_end": f_end,
                       "gap_end": f_end / float(np.sum(V.astype(np.float64) ** 2))},
     }
-    del Vd, Wd, Hd
+    del Wd, Hd
+    if not args.no_rank_sweep:
+        out["rank_sweep"] = rank_sweep(Vd, args, log)
+    del Vd
     torch.cuda.empty_cache()
     if not args.no_stream_reference:
         out["hbm_reference"] = stream_reference()
     if not args.no_precision_tier:
-        out["precision_tier"] = precision_tier_experiment(
-            args, lambda msg: print(msg, file=sys.stderr, flush=True))
+        out["precision_tier"] = precision_tier_experiment(args, log)
         torch.cuda.empty_cache()
     if not args.no_batch:
-        out["batched"] = batched_experiment(
-            args, lambda msg: print(msg, file=sys.stderr, flush=True))
+        out["batched"] = batched_experiment(args, log)
         torch.cuda.empty_cache()
     if not args.no_warm_start:
-        out["time_to_gap"] = warm_start_experiment(
-            args, lambda msg: print(msg, file=sys.stderr, flush=True))
+        out["time_to_gap"] = warm_start_experiment(args, log)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(V, W0, H0, args.cpu_seconds)
+        if args.cpu_gap_seconds > 0:
+            Wb = gen.warm_start_base()
+            Vm = gen.warm_start_matrix(Wb, 800)[0]
+            out["cpu_baseline"]["time_to_gap"] = oracle_time_to_gap(Vm, 800, args.cpu_gap_seconds)
     print(json.dumps(out), flush=True)
 
 

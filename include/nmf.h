@@ -111,6 +111,12 @@ nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n,
    timed. */
 nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
 
+/* Capture now every graph that nmf_step replays (use_graph), instead of on
+   first use, so that a later nmf_step only launches.  Records kernels into
+   graphs without running them: no device work is enqueued and W, H are
+   unchanged.  No-op without use_graph. */
+nmf_status nmf_prepare_graphs(nmf_ctx* ctx);
+
 /* Enqueue only the W half-step (eq. nnmf_v_update):
    W <- W * (V H^T) / (W (H H^T)), entries with a non-positive denominator
    kept unchanged.  Asynchronous. */
@@ -234,6 +240,43 @@ nmf_status nmf_mlp_get_params(nmf_mlp* m, float* M1, float* b1, float* M2,
 /* Release the network.  NULL is ignored. */
 void nmf_mlp_destroy(nmf_mlp* m);
 
+/* ---- Warm start: dictionary, prediction and training loop ---------------
+   The learned warm start hands a new matrix V a start (W0, H0) for the
+   multiplicative updates of Algorithm 1: W0 = the mean dictionary W-bar
+   (p x r) stored in the network object, H0 = the network applied to every
+   column of V.  The updates then refine it (they never increase f, so the
+   start affects the time to a tolerance, not the quality reached).  The
+   multiplicative method itself (Sec. 3.1) needs only a positive start; the
+   learned start is an addition to it. */
+
+/* Store W-bar (p x r row-major, device; p and r as in nmf_mlp_create),
+   copied in; replaces an earlier one.  Asynchronous on the network's
+   stream.  NMF_ENOMEM if its buffer cannot be allocated (first call). */
+nmf_status nmf_ws_set_dictionary(nmf_mlp* m, const float* Wbar);
+
+/* W0 (p x r, device) = the stored W-bar; H0 (r x n, row-major, device) =
+   the network applied to the n columns of V (p x n, row stride ldv,
+   device), as nmf_mlp_predict.  Asynchronous on the network's stream.
+   NMF_EINVAL if p differs from the network's input size or no dictionary
+   has been stored. */
+nmf_status nmf_ws_predict(nmf_mlp* m, const float* V, int64_t p, int64_t n,
+                          int64_t ldv, float* W0, float* H0);
+
+/* The training loop of the network, run by the library: `epochs` passes
+   over the `count` matrices V[i] (p x n, row stride ldv) with targets H[i]
+   (r x n, row stride ldh) -- host arrays of device pointers -- in a seeded
+   random order per epoch (Fisher-Yates driven by splitmix64 from `seed`),
+   each matrix in minibatches of `batch` consecutive columns (1 <= batch <=
+   the network's max_batch), one Adam step per minibatch (as
+   nmf_mlp_train_step, learning rate lr, multiplied by decay in (0, 1]
+   after every epoch).  Minibatch losses are summed on the device; the only
+   host synchronization is one per epoch when loss_host (may be NULL,
+   `epochs` doubles) receives each epoch's mean minibatch loss. */
+nmf_status nmf_ws_train(nmf_mlp* m, const float* const* V, const float* const* H,
+                        int32_t count, int64_t n, int64_t ldv, int64_t ldh,
+                        int32_t epochs, int32_t batch, float lr, float decay,
+                        uint64_t seed, double* loss_host);
+
 /* ---- Batched tier ----------------------------------------------------------
    Many independent problems V_b ~ W_b H_b of uneven p, n and r (r <= 64)
    advanced together: every call of nmf_batch_step is ONE persistent kernel
@@ -301,10 +344,29 @@ nmf_status nmf_batch_tune(nmf_batch* b, int32_t trial_iters, double* best_ms);
 /* Release the batch (not the caller's arrays).  NULL is ignored. */
 void nmf_batch_destroy(nmf_batch* b);
 
-/* Create, step `iters` iterations, write the objectives to f_out (host,
-   count doubles, may be NULL) and destroy. */
+/* Solve every problem of the list with one call: create a batch, run
+   chunks of opt->check_every iterations (one persistent launch each), after
+   each chunk evaluate every problem's objective and stop when every problem
+   satisfies the stopping rule of opt (tol_kind, tol: the rules of nmf_solve,
+   applied per problem) or max_iters iterations have run; then destroy the
+   batch.  Every problem runs the same number of iterations (the updates
+   never increase f, so iterations past a problem's own stopping point only
+   refine it).  opt may be NULL (defaults of nmf_default_options).
+   opt->seed != 0: W and H of problem i are first filled with U(0,1) draws
+   (Philox4x32-10 under key seed, streams 2i and 2i + 1; problem 0 gets the
+   start nmf_init draws for that seed).  opt->validate: every V is scanned
+   first and a negative or non-finite entry returns NMF_EINVAL.
+   opt->use_graph is ignored (the batched tier always replays its launch
+   from a graph).  opt->precision must be NMF_FP32 (NMF_EUNSUPPORTED
+   otherwise).  iters_done_host (may be NULL) receives the iterations run;
+   f_out (host, count doubles, may be NULL) the final objectives.
+   Returns NMF_OK when the rule held for every problem at a check,
+   NMF_ENOTCONVERGED at the cap (max_iters = 0: the start is evaluated
+   only), NMF_ENONFINITE if an objective is not finite, and the errors of
+   nmf_batch_create. */
 nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count,
-                           int32_t iters, double* f_out, void* stream);
+                           int32_t max_iters, const nmf_options* opt,
+                           int32_t* iters_done_host, double* f_out, void* stream);
 
 /* Release the context's workspace.  NULL is ignored. */
 void nmf_destroy(nmf_ctx* ctx);

@@ -786,7 +786,7 @@ __global__ __launch_bounds__(256) void k_batch_gram_h(const Prob* __restrict__ p
 // tile, summed per problem in tile order by k_batch_obj_sum.
 __global__ __launch_bounds__(256) void k_batch_objective(const Prob* __restrict__ probs,
                                                          const int4* __restrict__ tiles,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part, int zero_w) {
   __shared__ __attribute__((aligned(16))) float WsT[64 * 64];
   __shared__ __attribute__((aligned(16))) float Hs[64 * 64];
   __shared__ double red[4];
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(256) void k_batch_objective(const Prob* __restrict_
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) s[a][b] = 0.0;
-  for (int kk = 0; kk < rp; ++kk) {
+  for (int kk = 0; kk < (zero_w ? 0 : rp); ++kk) {  // zero_w: W = 0, f = ||V||^2
     const float4 w = lds4(&WsT[kk * 64 + 4 * ty]);
     const float4 h = lds4(&Hs[kk * 64 + 4 * tx]);
     const double wd[4] = {(double)w.x, (double)w.y, (double)w.z, (double)w.w};
@@ -1244,18 +1244,34 @@ nmf_status nmf_batch_check(nmf_batch* b) {
   return nmfb::check_error(b);
 }
 
-nmf_status nmf_batch_objective(nmf_batch* b, double* f_host) {
-  using namespace nmfb;
-  if (!b || !f_host) return NMF_EINVAL;
+}  // extern "C"
+
+namespace nmfb {
+namespace {
+
+// f[b] = ||V_b - W_b H_b||^2 (or ||V_b||^2 with zero_w) into the host
+// buffer; synchronizes.
+nmf_status batch_objectives(nmf_batch* b, int zero_w) {
   hipLaunchKernelGGL(k_batch_objective, dim3((unsigned)b->nobj), dim3(256), 0, b->st, b->dprobs,
-                     b->obj_tiles, b->obj_part);
+                     b->obj_tiles, b->obj_part, zero_w);
   BTRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_batch_obj_sum, dim3((unsigned)b->count), dim3(256), 0, b->st, b->obj_part,
                      b->obj_first, b->fdev);
   BTRY_HIP(hipGetLastError());
   BTRY_HIP(hipMemcpyAsync(b->hostbuf, b->fdev, b->count * sizeof(double), hipMemcpyDeviceToHost,
                           b->st));
-  BTRY(check_error(b));
+  return check_error(b);
+}
+
+}  // namespace
+}  // namespace nmfb
+
+extern "C" {
+
+nmf_status nmf_batch_objective(nmf_batch* b, double* f_host) {
+  using namespace nmfb;
+  if (!b || !f_host) return NMF_EINVAL;
+  BTRY(batch_objectives(b, 0));
   for (int i = 0; i < b->count; ++i) {
     if (!std::isfinite(b->hostbuf[i])) return NMF_ENONFINITE;
     f_host[i] = b->hostbuf[i];
@@ -1373,17 +1389,104 @@ void nmf_batch_destroy(nmf_batch* b) {
   delete b;
 }
 
-nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count, int32_t iters,
-                           double* f_out, void* stream) {
-  if (iters < 0) return NMF_EINVAL;
+nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count, int32_t max_iters,
+                           const nmf_options* opt, int32_t* iters_done, double* f_out,
+                           void* stream) {
+  using namespace nmfb;
+  if (max_iters < 0 || !probs || count < 1) return NMF_EINVAL;
+  nmf_options o;
+  nmf_default_options(&o);
+  if (opt) o = *opt;
+  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol) || o.reserved != 0)
+    return NMF_EINVAL;
+  if (o.precision != NMF_FP32) return NMF_EUNSUPPORTED;  // the batched tier is float32
+  if (o.tol_kind != NMF_TOL_REL_CHANGE && o.tol_kind != NMF_TOL_GAP_NORMALIZED)
+    return NMF_EUNSUPPORTED;
+  if (iters_done) *iters_done = 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // argument checks of nmf_batch_create before any device work
+  for (int32_t i = 0; i < count; ++i) {
+    const nmf_problem& P = probs[i];
+    if (!P.V || !P.W || !P.H || P.p < 1 || P.n < 1 || P.r < 1 || P.ldv < P.n || P.reserved != 0)
+      return NMF_EINVAL;
+    if (P.r > 64) return NMF_EUNSUPPORTED;
+  }
+  if (o.validate) {
+    uint32_t* flag = nullptr;
+    if (hipMalloc(&flag, sizeof(uint32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return NMF_ENOMEM;
+    }
+    nmf_status s = NMF_OK;
+    uint32_t bad = 0;
+    if (nmfk::launch_fill_u32(flag, 1, 0u, st) != hipSuccess) s = NMF_EDEVICE;
+    for (int32_t i = 0; i < count && s == NMF_OK; ++i)
+      if (nmfk::launch_validate(probs[i].V, probs[i].ldv, probs[i].p, probs[i].n, flag, st) !=
+          hipSuccess)
+        s = NMF_EDEVICE;
+    if (s == NMF_OK && (hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, st) !=
+                            hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess))
+      s = NMF_EDEVICE;
+    (void)hipFree(flag);
+    if (s != NMF_OK) return s;
+    if (bad) return NMF_EINVAL;
+  }
+  if (o.seed != 0) {
+    // Algorithm 1's U(0,1) start on the device: problem i draws W from
+    // Philox stream 2i and H from stream 2i + 1 under key seed (problem 0
+    // gets the draws of nmf_init with the same seed)
+    for (int32_t i = 0; i < count; ++i) {
+      const nmf_problem& P = probs[i];
+      if (nmfk::launch_uniform(P.W, P.p, P.r, P.r, o.seed, 2u * (uint32_t)i, st) != hipSuccess ||
+          nmfk::launch_uniform(P.H, P.r, P.n, P.n, o.seed, 2u * (uint32_t)i + 1u, st) !=
+              hipSuccess)
+        return NMF_EDEVICE;
+    }
+  }
   nmf_batch* b = nullptr;
   nmf_status s = nmf_batch_create(&b, probs, count, stream);
   if (s != NMF_OK) return s;
-  s = nmf_batch_step(b, iters);
-  if (s == NMF_OK && f_out) s = nmf_batch_objective(b, f_out);
-  if (s == NMF_OK && !f_out) s = nmf_batch_check(b);
+  std::vector<double> nv2(count, 0.0), fprev(count, 0.0);
+  if (o.tol_kind == NMF_TOL_GAP_NORMALIZED) {
+    s = batch_objectives(b, 1);
+    for (int32_t i = 0; s == NMF_OK && i < count; ++i) nv2[i] = b->hostbuf[i];
+  }
+  if (s == NMF_OK) s = batch_objectives(b, 0);
+  for (int32_t i = 0; s == NMF_OK && i < count; ++i) {
+    fprev[i] = b->hostbuf[i];
+    if (!std::isfinite(fprev[i])) s = NMF_ENONFINITE;
+  }
+  // chunks of check_every iterations (one persistent launch each), then the
+  // objectives of every problem; stop once every problem meets the rule
+  int32_t done_iters = 0;
+  bool all = false;
+  while (s == NMF_OK && done_iters < max_iters && !all) {
+    const int32_t todo = std::min(o.check_every, max_iters - done_iters);
+    s = nmf_batch_step(b, todo);
+    if (s == NMF_OK) s = batch_objectives(b, 0);
+    if (s != NMF_OK) break;
+    done_iters += todo;
+    all = true;
+    for (int32_t i = 0; i < count; ++i) {
+      const double f = b->hostbuf[i];
+      if (!std::isfinite(f)) {
+        s = NMF_ENONFINITE;
+        break;
+      }
+      const bool ok = (o.tol_kind == NMF_TOL_REL_CHANGE)
+                          ? std::fabs(f - fprev[i]) / (std::fabs(fprev[i]) + 1.0) < o.tol
+                          : (nv2[i] > 0.0 ? f / nv2[i] : 0.0) <= o.tol;
+      all = all && ok;
+      fprev[i] = f;
+    }
+  }
+  if (iters_done) *iters_done = done_iters;
+  if (f_out)
+    for (int32_t i = 0; i < count; ++i) f_out[i] = fprev[i];
   nmf_batch_destroy(b);
-  return s;
+  if (s != NMF_OK) return s;
+  return all ? NMF_OK : NMF_ENOTCONVERGED;
 }
 
 }  // extern "C"

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdint>
 #include <new>
+#include <vector>
 
 #include "../../include/nmf.h"
 #include "nmf_internal.h"
@@ -218,6 +219,14 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __re
 
 // dst (rows x ldd) = src (rows x cols, pitch lds) zero-padded, as bf16 or
 // float32 and optionally transposed.
+// acc[0] += loss[0] * scale: the minibatch loss (a float64 sum of squared
+// errors) added to the epoch's running total on the device, so a training
+// loop needs no host round trip per step.
+__global__ void k_loss_accum(const double* __restrict__ loss, double scale,
+                             double* __restrict__ acc) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) acc[0] += loss[0] * scale;
+}
+
 __global__ void k_pack(const float* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
                        float* __restrict__ dstf, uint16_t* __restrict__ dstb, int64_t ldd) {
   const int64_t total = rows * cols;
@@ -259,6 +268,10 @@ struct nmf_mlp {
   double *lossp = nullptr, *lossd = nullptr, *hostbuf = nullptr;
   DmaCfg cf1{}, cf2{}, cba{}, cg1{}, cg2{};
   int64_t step = 0;
+  // warm start: the mean dictionary W-bar (p x r) that nmf_ws_predict hands
+  // out as W0, and the device accumulator of nmf_ws_train's epoch loss
+  float* Wbar = nullptr;
+  double* lossacc = nullptr;
 };
 
 namespace {
@@ -527,9 +540,15 @@ nmf_status nmf_mlp_predict(nmf_mlp* m, const float* V, int64_t n, int64_t ldv, f
   return NMF_OK;
 }
 
-static nmf_status train_or_grad(nmf_mlp* m, const float* V, int64_t n, int64_t ldv,
-                                const float* T, int64_t ldt, float lr, double* loss_host,
-                                float* const* grads) {
+}  // extern "C"
+
+namespace {
+
+// One minibatch: forward with targets T, backward, then Adam (grads ==
+// nullptr) or the gradients exported to grads.  The loss partials are left
+// in m->lossp.
+nmf_status train_core(nmf_mlp* m, const float* V, int64_t n, int64_t ldv, const float* T,
+                      int64_t ldt, float lr, float* const* grads) {
   nmf_status s = check_batch(m, V, n, ldv);
   if (s != NMF_OK) return s;
   if (!T || reinterpret_cast<uintptr_t>(T) % 4 != 0 || ldt < n) return NMF_EINVAL;
@@ -542,6 +561,25 @@ static nmf_status train_or_grad(nmf_mlp* m, const float* V, int64_t n, int64_t l
   Plan pg1{}, pg2{};
   if (s == NMF_OK) s = backward(m, &pg1, &pg2);
   if (s == NMF_OK) s = adam_all(m, pg1, pg2, lr, grads, m->gtmp);
+  return s;
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): the seeded order of nmf_ws_train.
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+static nmf_status train_or_grad(nmf_mlp* m, const float* V, int64_t n, int64_t ldv,
+                                const float* T, int64_t ldt, float lr, double* loss_host,
+                                float* const* grads) {
+  nmf_status s = train_core(m, V, n, ldv, T, ldt, lr, grads);
   if (s != NMF_OK) return s;
   if (loss_host) {
     MTRY_HIP(launch_reduce_f64(m->lossp, m->Bp / 64, m->lossd, m->st));
@@ -575,9 +613,86 @@ nmf_status nmf_mlp_get_params(nmf_mlp* m, float* M1, float* b1, float* M2, float
   return NMF_OK;
 }
 
+nmf_status nmf_ws_set_dictionary(nmf_mlp* m, const float* Wbar) {
+  if (!m || !Wbar || reinterpret_cast<uintptr_t>(Wbar) % 4 != 0) return NMF_EINVAL;
+  const size_t bytes = sizeof(float) * (size_t)m->p * m->r;
+  if (!m->Wbar && hipMalloc(reinterpret_cast<void**>(&m->Wbar), bytes) != hipSuccess) {
+    m->Wbar = nullptr;
+    (void)hipGetLastError();
+    return NMF_ENOMEM;
+  }
+  MTRY_HIP(hipMemcpyAsync(m->Wbar, Wbar, bytes, hipMemcpyDeviceToDevice, m->st));
+  return NMF_OK;
+}
+
+nmf_status nmf_ws_predict(nmf_mlp* m, const float* V, int64_t p, int64_t n, int64_t ldv,
+                          float* W0, float* H0) {
+  if (!m || !W0 || reinterpret_cast<uintptr_t>(W0) % 4 != 0) return NMF_EINVAL;
+  if (p != m->p || !m->Wbar) return NMF_EINVAL;
+  if (!V || n < 1 || ldv < n || !H0 || reinterpret_cast<uintptr_t>(H0) % 4 != 0)
+    return NMF_EINVAL;
+  MTRY_HIP(hipMemcpyAsync(W0, m->Wbar, sizeof(float) * (size_t)m->p * m->r,
+                          hipMemcpyDeviceToDevice, m->st));
+  return nmf_mlp_predict(m, V, n, ldv, H0);
+}
+
+nmf_status nmf_ws_train(nmf_mlp* m, const float* const* V, const float* const* H, int32_t count,
+                        int64_t n, int64_t ldv, int64_t ldh, int32_t epochs, int32_t batch,
+                        float lr, float decay, uint64_t seed, double* loss_host) {
+  if (!m || !V || !H || count < 1 || n < 1 || ldv < n || ldh < n || epochs < 1) return NMF_EINVAL;
+  if (batch < 1 || batch > m->nmax) return NMF_EINVAL;
+  if (!(lr > 0.f) || !std::isfinite(lr) || !(decay > 0.f && decay <= 1.f)) return NMF_EINVAL;
+  for (int32_t i = 0; i < count; ++i)
+    if (!V[i] || !H[i] || reinterpret_cast<uintptr_t>(V[i]) % 4 != 0 ||
+        reinterpret_cast<uintptr_t>(H[i]) % 4 != 0)
+      return NMF_EINVAL;
+  if (!m->lossacc && hipMalloc(reinterpret_cast<void**>(&m->lossacc), 256) != hipSuccess) {
+    m->lossacc = nullptr;
+    (void)hipGetLastError();
+    return NMF_ENOMEM;
+  }
+  std::vector<int32_t> order(count);
+  for (int32_t i = 0; i < count; ++i) order[i] = i;
+  uint64_t rng = seed;
+  float rate = lr;
+  for (int32_t ep = 0; ep < epochs; ++ep) {
+    // matrices in a seeded random order (Fisher-Yates), minibatches of
+    // `batch` consecutive columns (column slices, no copies)
+    for (int32_t i = count - 1; i > 0; --i) {
+      const int32_t j = (int32_t)(splitmix64(rng) % (uint64_t)(i + 1));
+      std::swap(order[i], order[j]);
+    }
+    MTRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(m->lossacc), 2, 0u, m->st));
+    int64_t steps = 0;
+    for (int32_t q = 0; q < count; ++q) {
+      const float* Vm = V[order[q]];
+      const float* Hm = H[order[q]];
+      for (int64_t a = 0; a < n; a += batch) {
+        const int64_t nb = std::min<int64_t>(batch, n - a);
+        nmf_status s = train_core(m, Vm + a, nb, ldv, Hm + a, ldh, rate, nullptr);
+        if (s != NMF_OK) return s;
+        MTRY_HIP(launch_reduce_f64(m->lossp, m->Bp / 64, m->lossd, m->st));
+        hipLaunchKernelGGL(k_loss_accum, dim3(1), dim3(64), 0, m->st, m->lossd,
+                           1.0 / ((double)nb * (double)m->r), m->lossacc);
+        MTRY_HIP(hipGetLastError());
+        ++steps;
+      }
+    }
+    if (loss_host) {
+      MTRY_HIP(hipMemcpyAsync(m->hostbuf, m->lossacc, 8, hipMemcpyDeviceToHost, m->st));
+      MTRY_HIP(hipStreamSynchronize(m->st));
+      loss_host[ep] = m->hostbuf[0] / (double)steps;
+    }
+    rate *= decay;
+  }
+  return NMF_OK;
+}
+
 void nmf_mlp_destroy(nmf_mlp* m) {
   if (!m) return;
   (void)hipStreamSynchronize(m->st);
+  if (m->Wbar) (void)hipFree(m->Wbar);
+  if (m->lossacc) (void)hipFree(m->lossacc);
   if (m->ws) (void)hipFree(m->ws);
   if (m->hostbuf) (void)hipHostFree(m->hostbuf);
   delete m;

@@ -631,6 +631,14 @@ nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
   return NMF_OK;
 }
 
+nmf_status nmf_prepare_graphs(nmf_ctx* c) {
+  if (!c) return NMF_EINVAL;
+  if (!c->opt.use_graph) return NMF_OK;
+  for (int j = 0; j < kGraphLevels; ++j)
+    if (!c->gp[j]) TRY(capture(c, 1 << j, &c->gp[j]));
+  return NMF_OK;
+}
+
 nmf_status nmf_objective(nmf_ctx* c, double* f_host) {
   if (!c || !f_host) return NMF_EINVAL;
   double f;

@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
     lib.nmf_init.restype = c_int32
     lib.nmf_step.argtypes = [P, c_int32]
     lib.nmf_step.restype = c_int32
+    lib.nmf_prepare_graphs.argtypes = [P]
+    lib.nmf_prepare_graphs.restype = c_int32
     lib.nmf_update_w.argtypes = [P]
     lib.nmf_update_w.restype = c_int32
     lib.nmf_update_h.argtypes = [P]
@@ -111,6 +113,14 @@ def load(path: str = LIB_PATH):
     lib.nmf_mlp_grads.restype = c_int32
     lib.nmf_mlp_get_params.argtypes = [P, P, P, P, P]
     lib.nmf_mlp_get_params.restype = c_int32
+    lib.nmf_ws_set_dictionary.argtypes = [P, P]
+    lib.nmf_ws_set_dictionary.restype = c_int32
+    lib.nmf_ws_predict.argtypes = [P, P, c_int64, c_int64, c_int64, P, P]
+    lib.nmf_ws_predict.restype = c_int32
+    lib.nmf_ws_train.argtypes = [P, POINTER(P), POINTER(P), c_int32, c_int64, c_int64, c_int64,
+                                 c_int32, c_int32, ctypes.c_float, ctypes.c_float, c_uint64,
+                                 POINTER(c_double)]
+    lib.nmf_ws_train.restype = c_int32
     lib.nmf_mlp_destroy.argtypes = [P]
     lib.nmf_mlp_destroy.restype = None
     lib.nmf_destroy.argtypes = [P]
@@ -132,7 +142,8 @@ def load(path: str = LIB_PATH):
     lib.nmf_batch_tune.restype = c_int32
     lib.nmf_batch_destroy.argtypes = [P]
     lib.nmf_batch_destroy.restype = None
-    lib.nmf_batch_solve.argtypes = [POINTER(NmfProblem), c_int32, c_int32, POINTER(c_double), P]
+    lib.nmf_batch_solve.argtypes = [POINTER(NmfProblem), c_int32, c_int32, POINTER(NmfOptions),
+                                     POINTER(c_int32), POINTER(c_double), P]
     lib.nmf_batch_solve.restype = c_int32
     lib.nmf_strerror.argtypes = [c_int32]
     lib.nmf_strerror.restype = ctypes.c_char_p
@@ -216,6 +227,10 @@ class Nmf:
 
     def step(self, iters: int = 1):
         self._check(load().nmf_step(self._ctx, int(iters)), "nmf_step")
+
+    def prepare_graphs(self):
+        """Capture the iteration graphs now (no device work; W, H unchanged)."""
+        self._check(load().nmf_prepare_graphs(self._ctx), "nmf_prepare_graphs")
 
     def update_w(self):
         self._check(load().nmf_update_w(self._ctx), "nmf_update_w")
@@ -355,6 +370,47 @@ class Mlp:
                     "nmf_mlp_grads")
         return g, loss.value
 
+    def set_dictionary(self, Wbar):
+        """Store the mean dictionary W-bar (p x r float32 CUDA tensor) that
+        ws_predict hands out as W0."""
+        import torch
+        if Wbar.dtype != torch.float32 or not Wbar.is_cuda or tuple(Wbar.shape) != (self.p, self.r):
+            raise ValueError(f"W-bar must be a ({self.p}, {self.r}) float32 CUDA tensor")
+        self._wbar = Wbar.contiguous()
+        self._check(load().nmf_ws_set_dictionary(self._m, _ptr(self._wbar)),
+                    "nmf_ws_set_dictionary")
+
+    def ws_predict(self, V, W0=None, H0=None):
+        """Warm start for V (p, n): returns (W0 = W-bar, H0 = network(V))."""
+        import torch
+        p, n = V.shape
+        if W0 is None:
+            W0 = torch.empty((self.p, self.r), dtype=torch.float32, device=V.device)
+        if H0 is None:
+            H0 = torch.empty((self.r, n), dtype=torch.float32, device=V.device)
+        self._check(load().nmf_ws_predict(self._m, _ptr(V), p, n, V.stride(0), _ptr(W0),
+                                          _ptr(H0)), "nmf_ws_predict")
+        return W0, H0
+
+    def train_loop(self, Vs, Hs, epochs, lr, batch, decay=1.0, seed=0):
+        """The library's training loop (nmf_ws_train) over the pairs
+        (Vs[i], Hs[i]); returns the mean minibatch loss of every epoch."""
+        if len(Vs) != len(Hs) or not Vs:
+            raise ValueError("need as many target matrices as input matrices")
+        n, ldv, ldh = Vs[0].shape[1], Vs[0].stride(0), Hs[0].stride(0)
+        for V, H in zip(Vs, Hs):
+            _check_rows(V, H)
+            if V.shape != (self.p, n) or H.shape != (self.r, n) or V.stride(0) != ldv \
+                    or H.stride(0) != ldh:
+                raise ValueError("all matrices need the same shapes and row strides")
+        vp = (c_void_p * len(Vs))(*[V.data_ptr() for V in Vs])
+        hp = (c_void_p * len(Hs))(*[H.data_ptr() for H in Hs])
+        losses = (c_double * int(epochs))()
+        self._check(load().nmf_ws_train(self._m, vp, hp, len(Vs), n, ldv, ldh, int(epochs),
+                                        int(batch), float(lr), float(decay), int(seed), losses),
+                    "nmf_ws_train")
+        return list(losses)
+
     def params(self):
         import torch
         out = [torch.empty((self.hidden, self.p), device="cuda"),
@@ -394,6 +450,23 @@ def _problem_list(problems):
                              f"H {tuple(H.shape)} do not match")
         arr[i] = NmfProblem(V.data_ptr(), W.data_ptr(), H.data_ptr(), p, n, V.stride(0), r, 0)
     return arr
+
+
+def batch_solve(problems, max_iters, tol_kind="rel_change", tol=1e-9, check_every=1,
+                validate=False, seed=0, stream=None):
+    """nmf_batch_solve: solve every (V, W, H) of the list (W, H updated in
+    place) until every problem meets the stopping rule or max_iters.
+    Returns (converged, iters_done, objectives)."""
+    import numpy as np
+    arr = _problem_list(problems)
+    opts = options("fp32", tol_kind, tol, check_every, validate, seed, True)
+    it = c_int32()
+    out = (c_double * len(problems))()
+    st = load().nmf_batch_solve(arr, len(problems), int(max_iters), byref(opts), byref(it), out,
+                                _stream_handle(stream))
+    if st not in (NMF_OK, NMF_ENOTCONVERGED):
+        raise NmfError(st, "nmf_batch_solve")
+    return st == NMF_OK, it.value, np.array(out[:], dtype=np.float64)
 
 
 class Batch:

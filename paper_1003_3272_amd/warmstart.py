@@ -95,33 +95,26 @@ def make_network(params, Hs, max_batch):
 
 
 def inference_copy(net, max_batch):
-    """A copy of a trained network whose buffers take max_batch columns at
-    once, so a whole matrix is predicted in one pass instead of in chunks of
-    the training batch."""
-    return nmf.Mlp(net.params(), max_batch=max_batch)
+    """A copy of a trained network (and of its stored dictionary) whose
+    buffers take max_batch columns at once, so a whole matrix is predicted
+    in one pass instead of in chunks of the training batch."""
+    out = nmf.Mlp(net.params(), max_batch=max_batch)
+    if getattr(net, "_wbar", None) is not None:
+        out.set_dictionary(net._wbar)
+    return out
 
 
 def train(net, Vs, Hs, epochs, lr, batch=512, decay=0.9, seed=0, log=None):
     """Adam epochs over the (V_m, H_m) pairs in minibatches of `batch`
-    columns (column slices, no copies); matrices in a seeded random order
-    each epoch, the learning rate scaled by `decay` after each epoch.
-    Returns the mean minibatch loss of each epoch."""
-    import numpy as np
-    rng = np.random.default_rng(seed)
-    losses = []
-    rate = lr
-    for ep in range(epochs):
-        order = rng.permutation(len(Vs))
-        tot, cnt = 0.0, 0
-        for m in order:
-            V, H = Vs[m], Hs[m]
-            for a in range(0, V.shape[1], batch):
-                tot += net.train_step(V[:, a:a + batch], H[:, a:a + batch], rate, want_loss=True)
-                cnt += 1
-        losses.append(tot / cnt)
-        if log:
-            log(f"epoch {ep}: loss {losses[-1]:.4e} lr {rate:.2e}")
-        rate *= decay
+    columns, run by the library's training loop (nmf_ws_train: matrices in
+    a seeded random order each epoch, the learning rate scaled by `decay`
+    after each epoch).  Returns the mean minibatch loss of each epoch."""
+    losses = net.train_loop(Vs, Hs, epochs, lr, batch, decay=decay, seed=seed)
+    if log:
+        rate = lr
+        for ep, loss in enumerate(losses):
+            log(f"epoch {ep}: loss {loss:.4e} lr {rate:.2e}")
+            rate *= decay
     return losses
 
 
@@ -129,7 +122,8 @@ def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters
                  net=None, Wbar=None, seed=None, ls_floor=1e-3, hfit=20):
     """Time to reach f / ||V||_F^2 <= tol from a given start (V already on
     the device).  start: "cold" (device U(0,1) draw keyed by `seed`),
-    "wbar" (W-bar and a constant H), "net" (W-bar and H0 = net(V)),
+    "wbar" (W-bar and a constant H), "net" (nmf_ws_predict: the network's
+    stored W-bar and H0 = net(V)),
     "net_ls" (H0 = net(V), W0 refit to H0 by least squares) or "hfit_ls"
     (no network: H fitted to W-bar by `hfit` H-only multiplicative updates
     from a constant H, then W0 refit to that H).
@@ -149,10 +143,10 @@ def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters
         ctx = nmf.Nmf(V, W, H, precision=precision, tol_kind="gap", tol=tol,
                       check_every=check_every, seed=seed)
     else:
-        W = Wbar.clone()
         if start in ("net", "net_ls"):
-            H = net.predict(V)
+            W, H = net.ws_predict(V)       # W0 = the network's W-bar, H0 = network(V)
         elif start in ("wbar", "hfit_ls"):
+            W = Wbar.clone()
             H = torch.full((r, n), 1.0 / r, dtype=torch.float32, device=V.device)
         else:
             raise ValueError(f"unknown start {start!r}")

@@ -168,5 +168,30 @@ def test_batch_null_calls():
     assert lib.nmf_batch_get_table(None, t) == nmf.NMF_EINVAL
     assert lib.nmf_batch_set_table(None, t) == nmf.NMF_EINVAL
     assert lib.nmf_batch_tune(None, 1, None) == nmf.NMF_EINVAL
-    assert lib.nmf_batch_solve(None, 1, 1, None, None) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_solve(None, 1, 1, None, None, None, None) == nmf.NMF_EINVAL
     lib.nmf_batch_destroy(None)  # must not crash
+
+
+def test_batch_solve_checks_options_before_device_work():
+    lib = nmf.load()
+    arr = (nmf.NmfProblem * 1)(nmf.NmfProblem(FAKE, FAKE, FAKE, 8, 8, 8, 4, 0))
+    for kw, want in ((dict(precision="bf16"), nmf.NMF_EUNSUPPORTED),
+                     (dict(check_every=0), nmf.NMF_EINVAL), (dict(tol=-1.0), nmf.NMF_EINVAL)):
+        o = nmf.options(**kw)
+        assert lib.nmf_batch_solve(arr, 1, 5, ctypes.byref(o), None, None, None) == want, kw
+    o = nmf.options()
+    o.reserved = 1
+    assert lib.nmf_batch_solve(arr, 1, 5, ctypes.byref(o), None, None, None) == nmf.NMF_EINVAL
+    assert lib.nmf_batch_solve(arr, 1, -1, None, None, None, None) == nmf.NMF_EINVAL
+    bad = (nmf.NmfProblem * 1)(nmf.NmfProblem(FAKE, FAKE, FAKE, 8, 8, 8, 65, 0))
+    assert lib.nmf_batch_solve(bad, 1, 5, None, None, None, None) == nmf.NMF_EUNSUPPORTED
+
+
+def test_warm_start_calls_reject_bad_arguments():
+    lib = nmf.load()
+    P = ctypes.c_void_p
+    arr = (P * 1)(FAKE)
+    assert lib.nmf_ws_set_dictionary(None, FAKE) == nmf.NMF_EINVAL
+    assert lib.nmf_ws_predict(None, FAKE, 8, 8, 8, FAKE, FAKE) == nmf.NMF_EINVAL
+    assert lib.nmf_ws_train(None, arr, arr, 1, 8, 8, 8, 1, 8, 1e-3, 1.0, 0, None) == nmf.NMF_EINVAL
+    assert lib.nmf_prepare_graphs(None) == nmf.NMF_EINVAL

@@ -175,51 +175,159 @@ def test_batch_solve_matches_batch_object(gpu_lib, reference):
     with nmf.Batch(dev1) as b:
         b.step(5)
         f1 = b.objective()
-    arr = nmf._problem_list(dev2)
-    out = (ctypes.c_double * len(dev2))()
-    st = nmf.load().nmf_batch_solve(arr, len(dev2), 5, out, None)
-    assert st == nmf.NMF_OK
-    assert np.array_equal(np.array(out[:]), f1)
-    for (_, W, H), (_, W2, H2) in zip(dev1, dev2):
+    # tol = 0 never holds: exactly 5 iterations, as one launch (check_every
+    # 5) and as five launches with a check after each (check_every 1)
+    for ce in (5, 1):
+        dev2 = _device(host)
+        arr = nmf._problem_list(dev2)
+        out = (ctypes.c_double * len(dev2))()
+        it = ctypes.c_int32()
+        opts = nmf.options("fp32", "gap", 0.0, ce)
+        st = nmf.load().nmf_batch_solve(arr, len(dev2), 5, ctypes.byref(opts), ctypes.byref(it),
+                                        out, None)
+        assert st == nmf.NMF_ENOTCONVERGED and it.value == 5
+        assert np.array_equal(np.array(out[:]), f1)
+        for (_, W, H), (_, W2, H2) in zip(dev1, dev2):
+            assert torch.equal(W, W2) and torch.equal(H, H2)
+
+
+def test_batch_solve_stops_at_tolerance(gpu_lib, reference):
+    """nmf_batch_solve with the gap rule: it returns at the first check
+    where every problem has f / ||V||^2 <= tol (the oracle's gap), and its
+    factors are those of the batch object after as many iterations."""
+    from paper_1003_3272_amd import nmf
+    host, _ = reference
+    tol, ce = 2e-2, 10
+    dev = _device(host)
+    conv, iters, f = nmf.batch_solve(dev, 3000, tol_kind="gap", tol=tol, check_every=ce)
+    assert conv and iters % ce == 0 and iters > 0
+    nv2 = np.array([float(np.sum(np.asarray(V, np.float64) ** 2)) for V, _, _ in host])
+    assert np.all(f / nv2 <= tol)
+    dev1 = _device(host)
+    with nmf.Batch(dev1) as b:
+        b.step(iters - ce)
+        f_prev = b.objective()
+        b.step(ce)
+        f_end = b.objective()
+    assert np.array_equal(f_end, f)
+    assert np.any(f_prev / nv2 > tol)   # the check before did not pass yet
+    for (_, W, H), (_, W2, H2) in zip(dev, dev1):
         assert torch.equal(W, W2) and torch.equal(H, H2)
 
 
+def test_batch_solve_seeded_start_and_validation(gpu_lib, reference):
+    """opt.seed fills every problem's start on the device (problem 0 gets
+    nmf_init's draw for the same seed); opt.validate rejects a negative
+    entry in any V before any iteration."""
+    from paper_1003_3272_amd import nmf
+    host, _ = reference
+    dev = _device(host)
+    conv, iters, f = nmf.batch_solve(dev, 0, seed=1234)
+    assert not conv and iters == 0
+    V0 = dev[0][0]
+    W1, H1 = torch.empty_like(dev[0][1]), torch.empty_like(dev[0][2])
+    with nmf.Nmf(V0, W1, H1, seed=1234):
+        pass
+    assert torch.equal(dev[0][1], W1) and torch.equal(dev[0][2], H1)
+    for _, W, H in dev:
+        assert (W > 0).all() and (W < 1).all() and (H > 0).all() and (H < 1).all()
+    bad = _device(host)
+    bad[-1][0][3, 2] = -1.0
+    W_before = bad[0][1].clone()
+    with pytest.raises(nmf.NmfError) as e:
+        nmf.batch_solve(bad, 5, validate=True)
+    assert e.value.status == nmf.NMF_EINVAL
+    assert torch.equal(bad[0][1], W_before)
+
+
+def _selected(shapes):
+    """Problems of the 512-problem workload checked against the oracle: the
+    largest p, the largest n, the most work (p n r), the smallest, and the
+    largest problem of every padded-rank class (16, 32, 48, 64)."""
+    pick = {max(range(len(shapes)), key=lambda b: shapes[b][0]),
+            max(range(len(shapes)), key=lambda b: shapes[b][1]),
+            max(range(len(shapes)), key=lambda b: np.prod(shapes[b])),
+            min(range(len(shapes)), key=lambda b: np.prod(shapes[b]))}
+    for cls in range(4):
+        members = [b for b, (p, n, r) in enumerate(shapes) if (r + 15) // 16 - 1 == cls]
+        if members:
+            pick.add(max(members, key=lambda b: shapes[b][0] * shapes[b][1]))
+    return sorted(pick)
+
+
 def test_full_batched_workload(gpu_lib):
-    """512 problems, p ~ U{64..1024}, n ~ U{128..4096}, r ~ U{4..64}: the
-    objective of every problem does not increase from 50 to 200 iterations
-    (float32 slack 1e-6), factors stay finite and nonnegative, and the three
-    smallest problems match the oracle after 50 iterations (1e-5)."""
+    """512 problems, p ~ U{64..1024}, n ~ U{128..4096}, r ~ U{4..64}.
+    Selected problems (largest p, largest n, most work, smallest, the
+    largest of each rank class) match the oracle after 10 iterations
+    (factors within 1e-4, objective within 1e-5) under the default tile
+    table, the table the autotuner picks and a forced alternative table;
+    then the objective of every problem does not increase from 50 to 200
+    iterations (float32 slack 1e-6) and factors stay finite and
+    nonnegative."""
     from paper_1003_3272_amd import nmf
     shapes = g.batch_shapes()
-    dev, small = [], sorted(range(len(shapes)), key=lambda b: np.prod(shapes[b]))[:3]
-    host_small = {}
+    sel = _selected(shapes)
+    dev, starts, host_sel = [], [], {}
     for b, (p, n, r) in enumerate(shapes):
         V, W0, H0 = g.batch_problem(b, p, n, r)
-        if b in small:
-            host_small[b] = (V, W0, H0)
+        if b in sel:
+            host_sel[b] = (V, W0, H0)
+        starts.append((W0, H0))
         dev.append((torch.from_numpy(V).cuda(), torch.from_numpy(W0).cuda(),
                     torch.from_numpy(H0).cuda()))
+    ref = {}
+    for b in sel:
+        V, W0, H0 = host_sel[b]
+        W, H, tr = O.run(V, W0, H0, 10)
+        ref[b] = (W, H, tr[-1])
+
+    def restart(bt):
+        for (_, W, H), (W0, H0) in zip(dev, starts):
+            W.copy_(torch.from_numpy(W0))
+            H.copy_(torch.from_numpy(H0))
+        bt.load()
+
+    def check(bt, tag):
+        bt.step(10)
+        f10 = bt.objective()
+        for b in sel:
+            Wo, Ho, fo = ref[b]
+            what = (tag, b, shapes[b], bt.table)
+            assert rel(dev[b][1].cpu().numpy(), Wo) < 1e-4, what
+            assert rel(dev[b][2].cpu().numpy(), Ho) < 1e-4, what
+            assert abs(f10[b] - fo) <= 1e-5 * fo, what
+
     with nmf.Batch(dev) as bt:
+        check(bt, "default table")
+        restart(bt)
+        bt.tune(trial_iters=3)
+        tuned = bt.table
+        check(bt, "tuned table")
+        alt = [2, 2, 2, 2, 2, 2, 2, 2, 1] if tuned != [2, 2, 2, 2, 2, 2, 2, 2, 1] else \
+            [1, 2, 1, 2, 1, 2, 1, 2, 2]
+        bt.table = alt
+        restart(bt)
+        check(bt, "alternative table")
+        bt.table = tuned
+        restart(bt)
         bt.step(50)
         f50 = bt.objective()
         bt.step(150)
         f200 = bt.objective()
     assert np.all(np.isfinite(f200))
     assert np.all(f200 <= f50 * (1 + 1e-6)), np.max(f200 / f50)
-    for b in small:
-        V, W0, H0 = host_small[b]
-        _, _, tr = O.run(V, W0, H0, 50)
-        assert abs(f50[b] - tr[-1]) <= 1e-5 * tr[-1], (b, shapes[b], f50[b], tr[-1])
     for _, W, H in dev[::37]:
         assert torch.isfinite(W).all() and (W >= 0).all()
         assert torch.isfinite(H).all() and (H >= 0).all()
 
 
 def test_queue_modes_agree(gpu_lib, reference, monkeypatch):
-    """The XCD-local queues (each problem's tiles on one XCD, L1-only
-    coherence) and the single global queue (agent-scope release/acquire)
-    run the same tile arithmetic in the same reduction order: bit-identical
-    factors, both matching the oracle."""
+    """The XCD-local queues (each problem's tiles served by the workgroups
+    of one XCD) and the single global queue run the same tile arithmetic in
+    the same reduction order: bit-identical factors, both matching the
+    oracle.  In both modes every value passed between tiles is read and
+    written with device-scope accesses, and a tile's waves drain their
+    stores (vmcnt) before the counter that publishes it is advanced."""
     from paper_1003_3272_amd import nmf
     host, ref = reference
     out = []

@@ -129,3 +129,86 @@ def test_training_reduces_loss(gpu_lib):
     losses = [net.train_step(Vd, Hd, 3e-3) for _ in range(150)]
     assert losses[-1] < 0.3 * losses[0]
     net.close()
+
+
+def test_ws_predict_gives_dictionary_and_network_start(gpu_lib):
+    """nmf_ws_predict: W0 is the stored W-bar bit for bit and H0 is the
+    network's prediction for V, bit-identical to nmf_mlp_predict."""
+    from paper_1003_3272_amd import nmf
+    params, V, _ = _case(300, 128, 20, 700, seed=11)
+    rng = np.random.default_rng(12)
+    Wbar = torch.from_numpy(rng.uniform(0.1, 1.0, size=(300, 20)).astype(np.float32)).cuda()
+    net = nmf.Mlp(params, max_batch=256)   # 700 columns: three chunks
+    Vd = torch.from_numpy(V).cuda()
+    with pytest.raises(nmf.NmfError):      # no dictionary stored yet
+        net.ws_predict(Vd)
+    net.set_dictionary(Wbar)
+    W0, H0 = net.ws_predict(Vd)
+    torch.cuda.synchronize()
+    assert torch.equal(W0, Wbar)
+    assert torch.equal(H0, net.predict(Vd))
+    Y, _ = mo.forward(params, V.T, bf16=True)
+    assert rel(H0.cpu().numpy(), Y.T) < 1e-3
+    net.close()
+
+
+def test_ws_train_equals_its_adam_steps(gpu_lib):
+    """nmf_ws_train over one matrix (so the shuffled order is trivial) for
+    two epochs with decay 0.5 runs exactly the Adam steps of
+    nmf_mlp_train_step over the same minibatches (a ragged last one
+    included) with learning rates lr and lr/2: bit-identical weights, and
+    the epoch losses are the means of the step losses."""
+    from paper_1003_3272_amd import nmf
+    params, V, H = _case(300, 128, 20, 700, seed=13)
+    Vd, Hd = torch.from_numpy(V).cuda(), torch.from_numpy(H).cuda()
+    a = nmf.Mlp(params, max_batch=256)
+    b = nmf.Mlp(params, max_batch=256)
+    losses = a.train_loop([Vd], [Hd], epochs=2, lr=1e-3, batch=256, decay=0.5, seed=3)
+    ref = []
+    for lr in (1e-3, 5e-4):
+        steps = [b.train_step(Vd[:, c:c + 256], Hd[:, c:c + 256], lr) for c in range(0, 700, 256)]
+        ref.append(float(np.mean(steps)))
+    for x, y in zip(a.params(), b.params()):
+        assert torch.equal(x, y)
+    assert np.allclose(losses, ref, rtol=1e-12, atol=0)
+    assert losses[1] < losses[0]
+    a.close()
+    b.close()
+
+
+def test_ws_train_order_covers_every_matrix(gpu_lib):
+    """Several matrices: one epoch of nmf_ws_train equals the Adam steps over
+    the matrices in the order of its seeded Fisher-Yates shuffle (splitmix64,
+    written out here), and a different seed gives different weights."""
+    from paper_1003_3272_amd import nmf
+    mats = [_case(128, 128, 8, 256, seed=20 + i)[1:] for i in range(5)]
+    params = _case(128, 128, 8, 256, seed=20)[0]
+    dev = [(torch.from_numpy(V).cuda(), torch.from_numpy(H).cuda()) for V, H in mats]
+    M = (1 << 64) - 1
+
+    def splitmix(state):
+        state = (state + 0x9E3779B97F4A7C15) & M
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return state, z ^ (z >> 31)
+
+    order, st = list(range(5)), 99
+    for i in range(4, 0, -1):
+        st, z = splitmix(st)
+        j = z % (i + 1)
+        order[i], order[j] = order[j], order[i]
+    a = nmf.Mlp(params, max_batch=128)
+    b = nmf.Mlp(params, max_batch=128)
+    c = nmf.Mlp(params, max_batch=128)
+    a.train_loop([v for v, _ in dev], [h for _, h in dev], epochs=1, lr=1e-3, batch=128, seed=99)
+    c.train_loop([v for v, _ in dev], [h for _, h in dev], epochs=1, lr=1e-3, batch=128, seed=5)
+    for m in order:
+        Vd, Hd = dev[m]
+        for col in range(0, 256, 128):
+            b.train_step(Vd[:, col:col + 128], Hd[:, col:col + 128], 1e-3, want_loss=False)
+    for x, y in zip(a.params(), b.params()):
+        assert torch.equal(x, y)
+    assert not all(torch.equal(x, y) for x, y in zip(a.params(), c.params()))
+    for net in (a, b, c):
+        net.close()

@@ -33,6 +33,7 @@ def test_warm_start_pipeline_small(gpu_lib):
     TOL = 3e-4
     Hs = ws.fit_targets(train, Wbar, tol=TOL)
     net = ws.make_network(g.mlp_init(p, 128, r, 5), Hs, max_batch=128)
+    net.set_dictionary(Wbar)
     ws.train(net, train, Hs, epochs=12, lr=1e-3, batch=128)
     res = {k: [] for k in ("cold", "wbar", "net", "hfit_ls", "net_ls")}
     kw = dict(tol=TOL, check_every=1)  # every iteration counted
