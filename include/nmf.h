@@ -182,6 +182,18 @@ nmf_status nmf_profile_stop(nmf_ctx* ctx, double* ms_host, int32_t* launches_hos
 nmf_status nmf_normalize_gauge(float* W, int64_t p, int32_t r, float* H,
                                int64_t n, void* stream);
 
+/* nmf_normalize_gauge without any device allocation, for callers that
+   cannot allocate (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+   nmf_normalize_gauge; its r column norms live in a static device array of
+   NMF_MAX_RANK floats (1 KB per GPU, held until the process ends) instead of
+   a per-call allocation.  r > NMF_MAX_RANK returns NMF_EINVAL.  Every call
+   on one GPU shares that array: calls that overlap on one GPU (two streams,
+   or two host threads) race and must be serialized by the caller.
+   NMF_EDEVICE if the array's device address cannot be obtained. */
+nmf_status nmf_normalize_gauge_noalloc(float* W, int64_t p, int32_t r, float* H,
+                                       int64_t n, void* stream);
+
 /* Replace W by the least-squares fit to the current H (a warm start whose H
    came from elsewhere, e.g. nmf_mlp_predict):
      W = max(V H^T (H H^T + delta I)^-1, floor),

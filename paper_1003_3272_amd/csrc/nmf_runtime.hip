@@ -27,6 +27,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -823,5 +824,58 @@ nmf_status nmf_normalize_gauge(float* W, int64_t p, int32_t r, float* H, int64_t
 }
 
 int32_t nmf_version(void) { return 100; }
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of nmf_normalize_gauge_noalloc: the r column norms of W.  Every
+// GPU the library runs on holds its own copy at its own address until the
+// process ends.  In host code `scratch` names a host-side stand-in, never
+// the device memory: kernels get the per-device address that
+// hipGetSymbolAddress returns (scratch_on_device below).
+__device__ __align__(256) float scratch[NMF_MAX_RANK];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept; nullptr on failure.
+float* scratch_on_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+nmf_status nmf_normalize_gauge_noalloc(float* W, int64_t p, int32_t r, float* H, int64_t n,
+                                       void* stream) {
+  if (!W || !H || p < 1 || n < 1 || r < 1) return NMF_EINVAL;
+  if (r > NMF_MAX_RANK) return NMF_EINVAL;  // the scratch holds NMF_MAX_RANK norms
+  if (reinterpret_cast<uintptr_t>(W) % 4 != 0 || reinterpret_cast<uintptr_t>(H) % 4 != 0)
+    return NMF_EINVAL;
+  float* norms = scratch_on_device();
+  if (!norms) return NMF_EDEVICE;
+  // k_col_norms writes norms[0..r) before k_apply_gauge reads them (same
+  // stream), so nothing left by an earlier call is read.
+  const hipError_t e = launch_gauge(W, p, r, H, n, norms, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NMF_OK : NMF_EDEVICE;
+}
 
 }  // extern "C"

@@ -101,6 +101,8 @@ def load(path: str = LIB_PATH):
     lib.nmf_profile_stop.restype = c_int32
     lib.nmf_normalize_gauge.argtypes = [P, c_int64, c_int32, P, c_int64, P]
     lib.nmf_normalize_gauge.restype = c_int32
+    lib.nmf_normalize_gauge_noalloc.argtypes = [P, c_int64, c_int32, P, c_int64, P]
+    lib.nmf_normalize_gauge_noalloc.restype = c_int32
     lib.nmf_mlp_create.argtypes = [POINTER(P), c_int32, c_int32, c_int32, c_int64, P, P, P, P, P]
     lib.nmf_mlp_create.restype = c_int32
     lib.nmf_mlp_predict.argtypes = [P, P, c_int64, c_int64, P]
@@ -177,6 +179,17 @@ def normalize_gauge(W, H, stream=None):
                                     c_void_p(H.data_ptr()), H.shape[1], _stream_handle(stream))
     if st != NMF_OK:
         raise NmfError(st, "nmf_normalize_gauge")
+
+
+def normalize_gauge_noalloc(W, H, stream=None):
+    """normalize_gauge through the entry point that allocates no device
+    memory (its scratch is a static device array shared by every call on the
+    GPU: do not overlap calls on one GPU)."""
+    st = load().nmf_normalize_gauge_noalloc(c_void_p(W.data_ptr()), W.shape[0], W.shape[1],
+                                            c_void_p(H.data_ptr()), H.shape[1],
+                                            _stream_handle(stream))
+    if st != NMF_OK:
+        raise NmfError(st, "nmf_normalize_gauge_noalloc")
 
 
 def _stream_handle(stream):

@@ -194,4 +194,6 @@ def test_warm_start_calls_reject_bad_arguments():
     assert lib.nmf_ws_set_dictionary(None, FAKE) == nmf.NMF_EINVAL
     assert lib.nmf_ws_predict(None, FAKE, 8, 8, 8, FAKE, FAKE) == nmf.NMF_EINVAL
     assert lib.nmf_ws_train(None, arr, arr, 1, 8, 8, 8, 1, 8, 1e-3, 1.0, 0, None) == nmf.NMF_EINVAL
+    assert lib.nmf_normalize_gauge_noalloc(None, 8, 4, FAKE, 8, None) == nmf.NMF_EINVAL
+    assert lib.nmf_normalize_gauge_noalloc(FAKE, 8, 257, FAKE, 8, None) == nmf.NMF_EINVAL
     assert lib.nmf_prepare_graphs(None) == nmf.NMF_EINVAL
