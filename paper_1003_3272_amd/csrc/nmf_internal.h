@@ -44,6 +44,7 @@ struct GramRed {
   int count;
   int elems;
   float* G;
+  int at_end;  // V-streaming products: reduce after the main loop, not before
 };
 
 NtCfg nt_config(int rp, bool gram);

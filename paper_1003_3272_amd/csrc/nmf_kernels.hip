@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+
 #include "nmf_internal.h"
 
 namespace nmfk {
@@ -93,15 +94,16 @@ __device__ __forceinline__ void gram_reduce_slice(const GramRed& g) {
     float s = 0.f;
     if (e < g.elems) {
       int q = l32;
-      // 8 loads in flight, added in ascending q
-      for (; q + 7 * 32 < g.count; q += 8 * 32) {
-        float v[8];
+      // 16 loads in flight (one round trip for up to 512 partials), added
+      // in ascending q
+      for (; q < g.count; q += 16 * 32) {
+        float v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = g.part[(int64_t)(q + 32 * u) * g.elems + e];
+        for (int u = 0; u < 16; ++u)
+          v[u] = (q + 32 * u < g.count) ? g.part[(int64_t)(q + 32 * u) * g.elems + e] : 0.f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
+        for (int u = 0; u < 16; ++u) s += v[u];
       }
-      for (; q < g.count; q += 32) s += g.part[(int64_t)q * g.elems + e];
     }
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
@@ -476,8 +478,12 @@ __device__ __forceinline__ void lds_barrier() {
 template <int L, int S>
 __device__ __forceinline__ void wait_stage(int after) {
   // my loads of the stage being consumed are done once at most
-  // L * after loads (those of the `after` later stages) are outstanding
-  if (S >= 4 && after >= 3) wait_vm<(S >= 4 ? 3 * L : 0)>();
+  // L * after loads (those of the `after` later stages, after <= S - 2)
+  // are outstanding
+  static_assert((S - 2) * L < 64, "vmcnt holds at most 63 outstanding loads");
+  if (S >= 6 && after >= 4) wait_vm<(S >= 6 ? 4 * L : 0)>();
+  else if (S >= 5 && after >= 3) wait_vm<(S >= 5 ? 3 * L : 0)>();
+  else if (S >= 4 && after >= 3) wait_vm<(S >= 4 ? 3 * L : 0)>();
   else if (after >= 2) wait_vm<2 * L>();
   else if (after == 1) wait_vm<L>();
   else wait_vm<0>();
@@ -577,10 +583,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
   // st - 1, whose buffer is then refilled with stage st + S - 1.
   const int pre = nst < S - 1 ? nst : S - 1;
   for (int st = 0; st < pre; ++st) issue(st);
-  // Gram of the previous update, reduced here (under the latency of the
-  // first copies) so the next kernel can use it.  Its loads and stores only
-  // make the ring's vmcnt waits below stricter.
-  gram_reduce_slice(gr);
+  // Gram of the previous update, reduced by this kernel so the next one can
+  // use it: here, under the latency of the first copies (its loads and
+  // stores only make the ring's vmcnt waits below stricter), or with at_end
+  // after the loop, where it delays no stage (the default: measured faster).
+  if (!gr.at_end) gram_reduce_slice(gr);
   for (int st = 0; st < nst; ++st) {
     const int later = nst - 1 - st;
     wait_stage<L, S>(later < S - 2 ? later : S - 2);
@@ -589,6 +596,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
     compute(lds + (st % S) * STAGE);
   }
 
+  if (gr.at_end) gram_reduce_slice(gr);
   float* P = part + (int64_t)blockIdx.x * sp;
 #pragma unroll
   for (int i = 0; i < MB; ++i)
@@ -2051,6 +2059,9 @@ static const DmaEntry kDma[] = {
     DME(1, 2, 1, 2, 3),  // 14: 16 x 64    pass 2, r <= 16
     // all 256 ranks in one workgroup, so V^T is read once (BF16 pass 2)
     DME(8, 4, 2, 2, 3),  // 15: 256 x 128  pass 2, r = 256, 3 stages
+    // rank 256, BF16: all ranks in one workgroup of 8 waves (two per SIMD)
+    DME(4, 4, 4, 2, 3),  // 16: 256 x 128  pass 2, 3 stages (144 KB)
+    DME(4, 4, 2, 4, 3),  // 17: 128 x 256  pass 1, 3 stages
 };
 #undef DME
 static const int kDmaCount = sizeof(kDma) / sizeof(kDma[0]);
@@ -2066,9 +2077,11 @@ DmaCfg dma_config_by_id(int id) {
 }
 
 DmaCfg dma_config(int rp, bool pass1, bool narrow, bool bf16) {
-  // BF16 pass 2 at rank 256: one workgroup for all ranks (measured 13%
-  // faster there; in FP32, bound by the matrix cores, the 128 x 128 tile is)
-  if (rp == 256 && !pass1 && bf16) return dma_config_by_id(15);
+  // BF16 at rank 256: one workgroup of 8 waves for all 256 ranks, so V
+  // (pass 1) or V^T (pass 2) is read once (8192 x 32768: pass 2 186 -> 158
+  // us, pass 1 165 -> 160 us against 128 x 128 tiles; in FP32, bound by the
+  // matrix cores, the 128 x 128 tiles are as fast)
+  if (rp == 256 && bf16) return dma_config_by_id(pass1 ? 17 : 16);
   if (rp > 64) return dma_config_by_id(3);
   if (narrow) {
     if (pass1) return dma_config_by_id(rp == 16 ? 13 : rp == 32 ? 11 : 9);
