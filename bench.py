@@ -19,7 +19,8 @@ and on all of them.
 Then (unless --no-stream-reference) a plain 1.07 GB device copy by torch, as
 a practical HBM streaming rate beside the 8000 GB/s peak.
 Then (unless --no-rank-sweep) the same shape at ranks 8, 16, 32 and 64 in
-both tiers (the HBM-bound regime of the FP32 tier is rank <= 39).
+both tiers (the HBM-bound regime of the FP32 tier is rank <= 39), and (unless
+--no-poisson) the Poisson (KL) update at ranks 64 and 32.
 Then (unless --no-precision-tier) the FP32 and BF16 tiers at 8192 x 32768
 for ranks 32, 128 and 256, then (unless --no-batch) the batched tier: 512 problems of uneven shape,
 200 iterations each in one persistent launch, against a loop of the
@@ -69,6 +70,9 @@ def parse():
                     help="skip the rank sweep {8, 16, 32, 64} at the headline shape")
     ap.add_argument("--sweep-ranks", type=int, nargs="+", default=[8, 16, 32, 64])
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--no-poisson", action="store_true",
+                    help="skip the Poisson (KL) update at the headline shape")
+    ap.add_argument("--poisson-ranks", type=int, nargs="+", default=[64, 32])
     ap.add_argument("--pt-iters", type=int, default=200)
     ap.add_argument("--pt-ranks", type=int, nargs="+", default=[32, 128, 256])
     ap.add_argument("--pmc-calibration", action="store_true",
@@ -302,6 +306,48 @@ def rank_sweep(Vd, args, log):
             f"({res['fp32']['roofline']['bound']} {res['fp32']['roofline']['frac']}), bf16 "
             f"{res['bf16']['iters_per_s']} it/s ({res['bf16']['roofline']['bound']} "
             f"{res['bf16']['roofline']['frac']})")
+    return out
+
+
+def poisson_experiment(Vd, args, log):
+    """The Poisson (KL) square-root update on the headline matrix: iterations/s
+    on the default path and the roofline of the slower numerator pass.  Each
+    pass streams V (or V^T) once and runs 4 p n r flops on the matrix cores
+    (the B = W H values it needs, recomputed, and the numerator product)."""
+    import torch
+
+    from paper_1003_3272_amd import nmf
+    from synth import generators as gen
+    p, n = Vd.shape
+    out = {"workload": f"the headline V ({p}x{n}), Poisson log-likelihood, factorization rank "
+                       f"r, U(0,1) start seed 2002, fp32", "steps": args.sweep_steps, "ranks": {}}
+    for r in args.poisson_ranks:
+        W0, H0 = gen.uniform_init(p, n, r, seed=2002)
+        Wd, Hd = torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda()
+        with nmf.Nmf(Vd, Wd, Hd, loss="poisson") as ctx:
+            L0 = ctx.objective()
+            ctx.prepare_graphs()
+            ctx.step(4)
+            el = timed_steps(ctx, args.sweep_steps)
+            st = profiled_steps(ctx, min(args.sweep_steps, 50))
+            L1 = ctx.objective()
+        passes = {k: st[k][0] / max(1, st[k][1]) for k in ("gemm_vht", "gemm_wtv")}
+        dom = max(passes, key=passes.get)
+        ms = passes[dom]
+        flops = 4.0 * p * n * r
+        ach = flops / (ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK_TFLOPS["fp32"],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS["fp32"], 4), "kernel": dom,
+                "kernel_ms": round(ms, 4), "v_pass_gbs": round(4.0 * p * n / (ms * 1e-3) / 1e9, 1),
+                "flops_per_pass": "4 p n r (B = W H recomputed, then the numerator)"}
+        out["ranks"][str(r)] = {
+            "iters_per_s": round(args.sweep_steps / el, 1), "roofline": roof,
+            "stages_ms_per_iter": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()
+                                   if v[1] > 0},
+            "L_start": L0, "L_end": L1}
+        log(f"poisson r={r}: {out['ranks'][str(r)]['iters_per_s']} it/s, pass {ms * 1e3:.1f} us "
+            f"({roof['frac']} of FP32 MFMA)")
+        del Wd, Hd
     return out
 
 
@@ -656,6 +702,8 @@ def main():
     del Wd, Hd
     if not args.no_rank_sweep:
         out["rank_sweep"] = rank_sweep(Vd, args, log)
+    if not args.no_poisson:
+        out["poisson"] = poisson_experiment(Vd, args, log)
     del Vd
     torch.cuda.empty_cache()
     if not args.no_stream_reference:

@@ -45,7 +45,8 @@ typedef enum {
   NMF_ENOMEM = -2,        /* device allocation failed                        */
   NMF_EDEVICE = -3,       /* a HIP runtime call failed                       */
   NMF_ENONFINITE = -4,    /* the objective became NaN or Inf                 */
-  NMF_EUNSUPPORTED = -5   /* r above NMF_MAX_RANK, or an unknown option      */
+  NMF_EUNSUPPORTED = -5   /* r above NMF_MAX_RANK, an unknown option, or a
+                             combination of options not offered             */
 } nmf_status;
 
 typedef enum {
@@ -64,6 +65,19 @@ typedef enum {
   NMF_TOL_GAP_NORMALIZED = 1
 } nmf_tol_kind;
 
+typedef enum {
+  /* ||V - W H||_F^2, minimized (Sec. 3.1, eq. nnmf-objfn; Algorithm 1)     */
+  NMF_LOSS_EUCLIDEAN = 0,
+  /* Poisson log-likelihood L = sum_ij [v_ij ln b_ij - b_ij], b = W H,
+     maximized by the square-root multiplicative update of Sec. 3.1 (last
+     display): w_ik <- w_ik sqrt(sum_j (v_ij / b_ij) h_kj / sum_j h_kj),
+     h_kj <- h_kj sqrt(sum_i (v_ij / b_ij) w_ik / sum_i w_ik), both from the
+     same iterate (the display's second update, whose indices are garbled,
+     read as the mirror image of the first).  FP32 only, r <= 64, stopping
+     rule NMF_TOL_REL_CHANGE only; nmf_objective returns L.               */
+  NMF_LOSS_POISSON = 1
+} nmf_loss;
+
 #define NMF_MAX_RANK 256
 
 typedef struct {
@@ -81,11 +95,11 @@ typedef struct {
   int32_t use_graph;    /* nonzero: nmf_step replays the iteration's kernels
                            from a captured HIP graph (fewer launch gaps);
                            results are identical to direct launches        */
-  int32_t reserved;     /* must be 0                                        */
+  int32_t loss;         /* nmf_loss (NMF_LOSS_EUCLIDEAN by default)          */
 } nmf_options;
 
 /* Fill *opt with defaults: FP32, REL_CHANGE, tol 1e-9, check_every 1,
-   validate 0, seed 0, use_graph 1.  NULL is ignored. */
+   validate 0, seed 0, use_graph 1, Euclidean loss.  NULL is ignored. */
 void nmf_default_options(nmf_options* opt);
 
 /* Create a context for V (p x n, row stride ldv) and rank r, reading the
@@ -369,8 +383,8 @@ void nmf_batch_destroy(nmf_batch* b);
    start nmf_init draws for that seed).  opt->validate: every V is scanned
    first and a negative or non-finite entry returns NMF_EINVAL.
    opt->use_graph is ignored (the batched tier always replays its launch
-   from a graph).  opt->precision must be NMF_FP32 (NMF_EUNSUPPORTED
-   otherwise).  iters_done_host (may be NULL) receives the iterations run;
+   from a graph).  opt->precision must be NMF_FP32 and opt->loss
+   NMF_LOSS_EUCLIDEAN (NMF_EUNSUPPORTED otherwise).  iters_done_host (may be NULL) receives the iterations run;
    f_out (host, count doubles, may be NULL) the final objectives.
    Returns NMF_OK when the rule held for every problem at a check,
    NMF_ENOTCONVERGED at the cap (max_iters = 0: the start is evaluated

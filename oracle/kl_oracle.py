@@ -1,9 +1,9 @@
 """Plain FP64 CPU oracle for the Poisson (Kullback-Leibler) variant of
 multiplicative NMF, Sec. 3.1 (last two displays).
 
-TEST INFRASTRUCTURE ONLY.  Only the test suite may import this module; no
-GPU code implements this variant yet, and nothing here is shared with the
-HIP path.
+TEST INFRASTRUCTURE ONLY.  Only the test suite may import this module.  The
+GPU path (the library's NMF_LOSS_POISSON update) never calls it, and nothing
+here is shared with the HIP path.
 
 Letters as in nmf_oracle: data V (p x n) <- paper's X, W (p x r) <- paper's
 V, H (r x n) <- paper's W.  The objective, to be maximized, is the Poisson

@@ -1397,9 +1397,9 @@ nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count, int32_t max_
   nmf_options o;
   nmf_default_options(&o);
   if (opt) o = *opt;
-  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol) || o.reserved != 0)
-    return NMF_EINVAL;
-  if (o.precision != NMF_FP32) return NMF_EUNSUPPORTED;  // the batched tier is float32
+  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol)) return NMF_EINVAL;
+  // the batched tier runs the Euclidean update in float32
+  if (o.precision != NMF_FP32 || o.loss != NMF_LOSS_EUCLIDEAN) return NMF_EUNSUPPORTED;
   if (o.tol_kind != NMF_TOL_REL_CHANGE && o.tol_kind != NMF_TOL_GAP_NORMALIZED)
     return NMF_EUNSUPPORTED;
   if (iters_done) *iters_done = 0;

@@ -170,6 +170,33 @@ hipError_t launch_ls_refit(const float* G, int rp, int r, int64_t p, const float
                            int64_t ldp, int64_t sp, int splits, double* ginv,
                            uint32_t* maxbits, float floor_rel, float* Wp, float* Wcaller,
                            hipStream_t st);
+// ---- Poisson (KL) multiplicative update (padded ranks 16, 32, 64) --------
+// Tiles of the two numerator passes: pass 1 bm1 x bn1 (data rows x ranks),
+// pass 2 bm2 x bn2 (ranks x data columns); every tile holds all rp ranks.
+void kl_tiles(int rp, int* bm1, int* bn1, int* bm2, int* bn2);
+// part[s][m][c] = sum_k X'[m][k] Y'[c][k] with the data operand (pass 1: X =
+// V, pass 2: Y = V^T) replaced by V / (W H) (zero where V is zero); G is the
+// factor not streamed: pass 1 W (ppad x rp, ldg = rp), pass 2 H (rp x ldg).
+hipError_t launch_kl_pass(int rp, bool pass1, const float* X, int64_t ldx, int64_t M,
+                          const float* Y, int64_t ldy, int64_t N, int64_t K, int splits,
+                          int64_t kchunk, const float* G, int64_t ldg, float* part,
+                          int64_t ldp, int64_t sp, hipStream_t st);
+// den[k] = sum_{j<n} H[k][j], den[rp + k] = sum_{i<p} W[i][k] (float64 sums).
+hipError_t launch_kl_sums(const float* Wp, int rp, int64_t p, const float* Hp, int64_t ldh,
+                          int64_t n, float* den, hipStream_t st);
+// The square-root updates of W and H from the pass partials and den.
+hipError_t launch_kl_update_w(const float* part, int64_t ldp, int64_t sp, int splits,
+                              const float* den, float* Wp, int rp, int64_t p, int r, float* WT,
+                              int64_t ldwt, float* Wc, hipStream_t st);
+hipError_t launch_kl_update_h(const float* part, int64_t ldp, int64_t sp, int splits,
+                              const float* den, float* Hp, int64_t ldh, int rp, int64_t n,
+                              int r, float* Hc, hipStream_t st);
+// Poisson objective partials, one double per 64 x 64 tile (grid as
+// launch_objective): sum [v ln b - b], b = W H in float64, 0 ln 0 = 0.
+hipError_t launch_kl_objective(int rp, const float* V, int64_t ldv, int64_t p, int64_t n,
+                               const float* Wp, const float* Hp, int64_t ldh, double* part,
+                               hipStream_t st);
+
 // flag |= 1 if some V entry is negative or non-finite.
 hipError_t launch_validate(const float* V, int64_t ldv, int64_t p, int64_t n,
                            uint32_t* flag, hipStream_t st);

@@ -134,6 +134,8 @@ struct nmf_ctx {
   hipEvent_t chk_ev[2] = {nullptr, nullptr};  // solve: check values written
 
   bool bf16 = false;
+  bool kl = false;        // Poisson (KL) square-root update instead of Euclidean
+  float* kl_den = nullptr;  // Poisson: 2 x rp denominators (row sums of H, column sums of W)
   bool fuse = false;      // rp <= 64: Grams formed in the update kernels
   int gram_at_end = 0;    // the products reduce the Gram partials after their loop
   int uw_grid = 1, uh_grid = 1;
@@ -277,11 +279,57 @@ nmf_status half_h(nmf_ctx* c) {
   return c->fuse ? NMF_OK : gram_h(c);
 }
 
+// One iteration of the Poisson update (both factors from the same iterate):
+// the two denominators, the two numerator passes over V and V^T (each
+// recomputing its B = W H values on the matrix cores), then the square-root
+// updates of W and H.  The denominator kernel is timed as the W Gram stage.
+nmf_status kl_iter(nmf_ctx* c) {
+  {
+    StageTimer t(c, NMF_STAGE_GRAM_W);
+    TRY_HIP(launch_kl_sums(c->Wp, c->rp, c->p, c->Hp, c->npad, c->n, c->kl_den, c->st));
+  }
+  {
+    StageTimer t(c, NMF_STAGE_GEMM_VHT);
+    TRY_HIP(launch_kl_pass(c->rp, true, c->Vk, c->ldvk, c->p, c->Hp, c->npad, c->rp, c->npad,
+                           c->s1.splits, c->s1.kchunk, c->Wp, c->rp, c->part1, c->s1.ldp,
+                           c->s1.sp, c->st));
+  }
+  {
+    StageTimer t(c, NMF_STAGE_GEMM_WTV);
+    TRY_HIP(launch_kl_pass(c->rp, false, c->WT, c->lwt, c->rp, c->VT, c->lvt, c->n, c->ppad,
+                           c->s2.splits, c->s2.kchunk, c->Hp, c->npad, c->part2, c->s2.ldp,
+                           c->s2.sp, c->st));
+  }
+  {
+    StageTimer t(c, NMF_STAGE_UPDATE_W);
+    TRY_HIP(launch_kl_update_w(c->part1, c->s1.ldp, c->s1.sp, c->s1.splits, c->kl_den, c->Wp,
+                               c->rp, c->p, c->r, c->WT, c->lwt, c->Wuser, c->st));
+  }
+  {
+    StageTimer t(c, NMF_STAGE_UPDATE_H);
+    TRY_HIP(launch_kl_update_h(c->part2, c->s2.ldp, c->s2.sp, c->s2.splits, c->kl_den, c->Hp,
+                               c->npad, c->rp, c->n, c->r, c->Huser, c->st));
+  }
+  return NMF_OK;
+}
+
+// One full iteration of the context's method.
+nmf_status iterate(nmf_ctx* c) {
+  if (c->kl) return kl_iter(c);
+  TRY(half_w(c));
+  return half_h(c);
+}
+
 // Objective partials and their float64 reduction into out (device memory,
 // or the mapped pinned host buffer: then no copy operation is needed).
 nmf_status objective_async(nmf_ctx* c, const float* Wp, double* out) {
   StageTimer t(c, NMF_STAGE_OBJECTIVE);
-  TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart, c->st));
+  if (c->kl && Wp)
+    TRY_HIP(launch_kl_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart,
+                                c->st));
+  else
+    TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart,
+                             c->st));
   TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, out, c->st));
   return NMF_OK;
 }
@@ -321,10 +369,7 @@ nmf_status capture(nmf_ctx* c, int32_t iters, hipGraphExec_t* out) {
     c->st = user;
     return NMF_EDEVICE;
   }
-  for (int32_t it = 0; it < iters && s == NMF_OK; ++it) {
-    s = half_w(c);
-    if (s == NMF_OK) s = half_h(c);
-  }
+  for (int32_t it = 0; it < iters && s == NMF_OK; ++it) s = iterate(c);
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
   c->st = user;
   if (s != NMF_OK) {
@@ -394,12 +439,21 @@ nmf_status setup(nmf_ctx* c) {
   if (!fits1(c->d1) || !fits2(c->d2)) return NMF_EUNSUPPORTED;
   c->s1 = plan_split(p, rp, npad, c->d1.bm, c->d1.bn, 256, target, 1);
   c->s2 = plan_split(rp, n, ppad, c->d2.bm, c->d2.bn, 256, target2, 1);
-  c->fuse = rp <= 64;
+  c->kl = (c->opt.loss == NMF_LOSS_POISSON);
+  if (c->kl) {
+    // every tile holds all padded ranks (pass 1: 128 data rows, pass 2: 128
+    // data columns); split-K partials as for the Euclidean passes
+    int bm1, bn1, bm2, bn2;
+    kl_tiles(rp, &bm1, &bn1, &bm2, &bn2);
+    c->s1 = plan_split(p, rp, npad, bm1, bn1, 256, target, 1);
+    c->s2 = plan_split(rp, n, ppad, bm2, bn2, 256, target2, 1);
+  }
+  c->fuse = rp <= 64 && !c->kl;
   // the products reduce the previous update's Gram partials after their own
   // loop (4096 x 16384, rank 64, FP32: 82.5 -> 80.7 us per pass against
   // before it); NMF_GRAM_AT_END=0 restores the reduction before the loop
   c->gram_at_end = env_int("NMF_GRAM_AT_END", 1) == 0 ? 0 : 1;
-  if (!c->fuse) {
+  if (!c->fuse && !c->kl) {
     if (!c->bf16) {
       c->cgh = nt_config(rp, true);
       c->cgw = tn_config(rp, true);
@@ -435,7 +489,7 @@ nmf_status setup(nmf_ctx* c) {
   const size_t oGW = take(sizeof(float) * (size_t)rp * rp);
   const size_t o1 = take(sizeof(float) * (size_t)c->s1.splits * c->s1.sp);
   const size_t o2 = take(sizeof(float) * (size_t)c->s2.splits * c->s2.sp);
-  const size_t og = c->fuse ? 0
+  const size_t og = (c->fuse || c->kl) ? 0
                             : take(sizeof(float) * std::max((size_t)c->sgh.splits * c->sgh.sp,
                                                             (size_t)c->sgw.splits * c->sgw.sp));
   const size_t ogw = c->fuse ? take(sizeof(float) * (size_t)c->uw_grid * rp * rp) : 0;
@@ -443,6 +497,7 @@ nmf_status setup(nmf_ctx* c) {
   const size_t ofp = take(sizeof(double) * (size_t)c->nparts);
   const size_t ofl = take(sizeof(uint32_t) * 4);
   const size_t oli = c->fuse ? take(sizeof(double) * (size_t)rp * rp) : 0;
+  const size_t okl = c->kl ? take(sizeof(float) * 2 * (size_t)rp) : 0;
   size_t oVT = 0, oWT = 0, oVb = 0, oVTb = 0, oHb = 0, oWbT = 0;
   if (!c->bf16) {
     oVT = take(sizeof(float) * (size_t)npad * c->lvt);
@@ -466,7 +521,7 @@ nmf_status setup(nmf_ctx* c) {
   c->GW = reinterpret_cast<float*>(base + oGW);
   c->part1 = reinterpret_cast<float*>(base + o1);
   c->part2 = reinterpret_cast<float*>(base + o2);
-  if (!c->fuse) c->partg = reinterpret_cast<float*>(base + og);
+  if (!c->fuse && !c->kl) c->partg = reinterpret_cast<float*>(base + og);
   if (c->fuse) {
     c->gpw = reinterpret_cast<float*>(base + ogw);
     c->gph = reinterpret_cast<float*>(base + ogh);
@@ -474,6 +529,7 @@ nmf_status setup(nmf_ctx* c) {
   c->fpart = reinterpret_cast<double*>(base + ofp);
   c->flag = reinterpret_cast<uint32_t*>(base + ofl);
   if (c->fuse) c->lsinv = reinterpret_cast<double*>(base + oli);
+  if (c->kl) c->kl_den = reinterpret_cast<float*>(base + okl);
   if (!c->bf16) {
     c->VT = reinterpret_cast<float*>(base + oVT);
     c->WT = reinterpret_cast<float*>(base + oWT);
@@ -536,7 +592,7 @@ nmf_status setup(nmf_ctx* c) {
                             nullptr, 0, c->bf16, c->gpw, c->uw_grid, c->uw_kpt, true, c->st));
     TRY_HIP(launch_update_h(rp, n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, npad, c->Huser,
                             nullptr, c->bf16, c->gph, c->uh_grid, c->uh_cols, true, c->st));
-  } else {
+  } else if (!c->kl) {
     TRY(gram_h(c));
     TRY(gram_w(c));
   }
@@ -556,7 +612,7 @@ void nmf_default_options(nmf_options* opt) {
   opt->validate = 0;
   opt->seed = 0;
   opt->use_graph = 1;
-  opt->reserved = 0;
+  opt->loss = NMF_LOSS_EUCLIDEAN;
 }
 
 nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n, int64_t ldv, int32_t r,
@@ -570,12 +626,16 @@ nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n, int64_t
   TRY(check_ptr(V));
   TRY(check_ptr(W));
   TRY(check_ptr(H));
-  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol) || o.reserved != 0)
-    return NMF_EINVAL;
+  if (o.check_every < 1 || !(o.tol >= 0.0) || !std::isfinite(o.tol)) return NMF_EINVAL;
   if (o.precision != NMF_FP32 && o.precision != NMF_BF16) return NMF_EUNSUPPORTED;
   if (o.tol_kind != NMF_TOL_REL_CHANGE && o.tol_kind != NMF_TOL_GAP_NORMALIZED)
     return NMF_EUNSUPPORTED;
+  if (o.loss != NMF_LOSS_EUCLIDEAN && o.loss != NMF_LOSS_POISSON) return NMF_EUNSUPPORTED;
   if (r > NMF_MAX_RANK || p > kMaxDim || n > kMaxDim) return NMF_EUNSUPPORTED;
+  // the Poisson update: float32, padded rank <= 64, relative-change rule
+  if (o.loss == NMF_LOSS_POISSON &&
+      (o.precision != NMF_FP32 || r > 64 || o.tol_kind != NMF_TOL_REL_CHANGE))
+    return NMF_EUNSUPPORTED;
 
   nmf_ctx* c = new (std::nothrow) nmf_ctx();
   if (!c) return NMF_ENOMEM;
@@ -606,21 +666,20 @@ nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n, int64_t
 
 nmf_status nmf_update_w(nmf_ctx* c) {
   if (!c) return NMF_EINVAL;
+  if (c->kl) return NMF_EUNSUPPORTED;  // the Poisson update has no half-steps
   return half_w(c);
 }
 
 nmf_status nmf_update_h(nmf_ctx* c) {
   if (!c) return NMF_EINVAL;
+  if (c->kl) return NMF_EUNSUPPORTED;
   return half_h(c);
 }
 
 nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
   if (!c || iters < 0) return NMF_EINVAL;
   if (!c->opt.use_graph || c->prof) {
-    for (int32_t it = 0; it < iters; ++it) {
-      TRY(half_w(c));
-      TRY(half_h(c));
-    }
+    for (int32_t it = 0; it < iters; ++it) TRY(iterate(c));
     return NMF_OK;
   }
   // the largest graph while it fits, then the binary digits of the rest
@@ -734,7 +793,7 @@ nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double*
 
 nmf_status nmf_refit_w(nmf_ctx* c, float floor_rel) {
   if (!c || !(floor_rel > 0.f && floor_rel < 1.f)) return NMF_EINVAL;
-  if (!c->fuse || c->rp > 64) return NMF_EUNSUPPORTED;
+  if (c->kl || !c->fuse || c->rp > 64) return NMF_EUNSUPPORTED;
   // A = V H^T as in the W half-step; the same launch reduces G_H
   const GramRed gr = GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH};
   const void* X = c->bf16 ? static_cast<const void*>(c->Vb) : static_cast<const void*>(c->Vk);

@@ -24,11 +24,13 @@ NMF_EUNSUPPORTED = -5
 
 FP32, BF16 = 0, 1
 REL_CHANGE, GAP_NORMALIZED = 0, 1
+EUCLIDEAN, POISSON = 0, 1
 MAX_RANK = 256
 STAGES = ("gemm_vht", "update_w", "gram_w", "gemm_wtv", "update_h", "gram_h", "objective")
 
 _PRECISION = {"fp32": FP32, "bf16": BF16}
 _TOL = {"rel_change": REL_CHANGE, "gap": GAP_NORMALIZED, "gap_normalized": GAP_NORMALIZED}
+_LOSS = {"euclidean": EUCLIDEAN, "poisson": POISSON, "kl": POISSON}
 
 
 class NmfOptions(ctypes.Structure):
@@ -40,7 +42,7 @@ class NmfOptions(ctypes.Structure):
         ("validate", c_int32),
         ("seed", c_uint64),
         ("use_graph", c_int32),
-        ("reserved", c_int32),
+        ("loss", c_int32),
     ]
 
 
@@ -160,7 +162,7 @@ def strerror(status: int) -> str:
 
 
 def options(precision="fp32", tol_kind="rel_change", tol=1e-9, check_every=1,
-            validate=False, seed=0, use_graph=True) -> NmfOptions:
+            validate=False, seed=0, use_graph=True, loss="euclidean") -> NmfOptions:
     o = NmfOptions()
     load().nmf_default_options(byref(o))
     o.precision = _PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -170,6 +172,7 @@ def options(precision="fp32", tol_kind="rel_change", tol=1e-9, check_every=1,
     o.validate = 1 if validate else 0
     o.seed = int(seed)
     o.use_graph = 1 if use_graph else 0
+    o.loss = _LOSS[loss] if isinstance(loss, str) else int(loss)
     return o
 
 
@@ -199,14 +202,17 @@ def _stream_handle(stream):
 
 
 class Nmf:
-    """One factorization context over torch CUDA tensors.
+    """One factorization context over torch CUDA tensors (loss "euclidean":
+    the multiplicative update of ||V - W H||^2; "poisson": the square-root
+    update of the Poisson log-likelihood, whose objective() returns L).
 
     V: (p, n) float32 CUDA tensor with unit column stride (any row stride).
     W: (p, r) and H: (r, n) contiguous float32 CUDA tensors, updated in place.
     """
 
     def __init__(self, V, W, H, precision="fp32", tol_kind="rel_change", tol=1e-9,
-                 check_every=1, validate=False, seed=0, use_graph=True, stream=None):
+                 check_every=1, validate=False, seed=0, use_graph=True, stream=None,
+                 loss="euclidean"):
         import torch
         lib = load()
         for name, t in (("V", V), ("W", W), ("H", H)):
@@ -223,7 +229,8 @@ class Nmf:
         self._keep = (V, W, H)
         self.V, self.W, self.H = V, W, H
         self.p, self.n, self.r = p, n, r
-        self.opts = options(precision, tol_kind, tol, check_every, validate, seed, use_graph)
+        self.opts = options(precision, tol_kind, tol, check_every, validate, seed, use_graph,
+                            loss)
         self.stream = stream
         self._ctx = c_void_p()
         st = lib.nmf_init(byref(self._ctx), c_void_p(V.data_ptr()), p, n, V.stride(0), r,

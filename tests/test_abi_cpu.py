@@ -47,7 +47,7 @@ def test_default_options():
     o = nmf.NmfOptions()
     nmf.load().nmf_default_options(ctypes.byref(o))
     assert (o.precision, o.tol_kind, o.tol, o.check_every, o.validate, o.seed,
-            o.use_graph, o.reserved) == (0, 0, 1e-9, 1, 0, 0, 1, 0)
+            o.use_graph, o.loss) == (0, 0, 1e-9, 1, 0, 0, 1, 0)
 
 
 def test_strerror_and_version():
@@ -97,7 +97,7 @@ def test_init_rejects_rank_above_max():
     ("tol", float("inf"), nmf.NMF_EINVAL),
     ("precision", 7, nmf.NMF_EUNSUPPORTED),
     ("tol_kind", 5, nmf.NMF_EUNSUPPORTED),
-    ("reserved", 3, nmf.NMF_EINVAL),
+    ("loss", 3, nmf.NMF_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_options(field, value, code):
     o = nmf.options()
@@ -179,9 +179,9 @@ def test_batch_solve_checks_options_before_device_work():
                      (dict(check_every=0), nmf.NMF_EINVAL), (dict(tol=-1.0), nmf.NMF_EINVAL)):
         o = nmf.options(**kw)
         assert lib.nmf_batch_solve(arr, 1, 5, ctypes.byref(o), None, None, None) == want, kw
-    o = nmf.options()
-    o.reserved = 1
-    assert lib.nmf_batch_solve(arr, 1, 5, ctypes.byref(o), None, None, None) == nmf.NMF_EINVAL
+    o = nmf.options(loss="poisson")
+    assert lib.nmf_batch_solve(arr, 1, 5, ctypes.byref(o), None, None, None) == \
+        nmf.NMF_EUNSUPPORTED
     assert lib.nmf_batch_solve(arr, 1, -1, None, None, None, None) == nmf.NMF_EINVAL
     bad = (nmf.NmfProblem * 1)(nmf.NmfProblem(FAKE, FAKE, FAKE, 8, 8, 8, 65, 0))
     assert lib.nmf_batch_solve(bad, 1, 5, None, None, None, None) == nmf.NMF_EUNSUPPORTED
@@ -197,3 +197,11 @@ def test_warm_start_calls_reject_bad_arguments():
     assert lib.nmf_normalize_gauge_noalloc(None, 8, 4, FAKE, 8, None) == nmf.NMF_EINVAL
     assert lib.nmf_normalize_gauge_noalloc(FAKE, 8, 257, FAKE, 8, None) == nmf.NMF_EINVAL
     assert lib.nmf_prepare_graphs(None) == nmf.NMF_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(precision="bf16"), dict(tol_kind="gap"), dict(r=65)])
+def test_poisson_loss_rejects_options_it_does_not_offer(kw):
+    r = kw.pop("r", 8)
+    o = nmf.options(loss="poisson", **kw)
+    st, _ = _init(opt=o, r=r)
+    assert st == nmf.NMF_EUNSUPPORTED
