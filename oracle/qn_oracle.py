@@ -28,6 +28,15 @@ does not increase the objective compared with the plain MM point F(F(x));
 otherwise the iteration falls back to F(F(x)).  So the objective never
 increases, and a fixed point of F stays fixed.
 
+Positivity.  NMF's iterates live in the positive orthant, and the
+extrapolated point leaves it often: on the sparse warm-start matrices every
+extrapolation but one in 900 had a negative entry, so the rejection-only
+form above never accelerated.  The extrapolated point is therefore first
+projected onto the box x >= kappa F(x) (entrywise; kappa = 0.5), which keeps
+every entry at least a fixed fraction of its plain MM value, and the
+projected point is what the objective test accepts or rejects.  kappa = 0
+gives the rejection-only form.
+
 Readings of points the method leaves open (the same on the GPU):
   * the first q QN iterations use the pairs collected so far (fewer than q
     columns); with no usable pair (a singular q x q system, e.g. u = 0 at a
@@ -37,7 +46,11 @@ Readings of points the method leaves open (the same on the GPU):
     that F itself sets to zero (e.g. the H column of an all-zero V column)
     is zero in x_qn too, so requiring strict positivity everywhere would
     switch the acceleration off for good on such data;
-  * the acceptance test compares f(x_qn) <= f(F(F(x))) exactly.
+  * the acceptance test compares f(x_qn) <= f(F(F(x))) exactly;
+  * the projection onto x >= kappa F(x) above (measured on 512 x 1024 warm-
+    start matrices, rank 24, to the 1e-4 gap: QN(4) needed 0.12 and 0.22 of
+    plain MM's map evaluations with kappa = 0.5; 0.19-0.44 with 0.25 or
+    0.75; q = 3 or 6 did worse than 4).
 """
 from __future__ import annotations
 
@@ -77,15 +90,21 @@ def qn_step(U, V, x, Fx, rcond=1e-12):
     return Fx + V @ c
 
 
+def project(xq, Fx, kappa):
+    """Entrywise max(x_qn, kappa F(x))."""
+    return np.maximum(xq, kappa * Fx)
+
+
 def solve(V, W0, H0, q, max_mm, tol=None, tol_kind=nmf.GAP_NORMALIZED, check_every=1,
-          step=None, objective=None):
+          step=None, objective=None, kappa=0.5):
     """QN(q)-accelerated multiplicative NMF from (W0, H0), float64.
 
     Runs QN iterations (two evaluations of the map F = one Algorithm 1
     iteration each) until `max_mm` evaluations of F, or until the stopping
     rule (the one of nmf_oracle.solve, evaluated on the accepted iterates
     every `check_every` QN iterations) holds.  `step(V, W, H) -> (W, H)` and
-    `objective(V, W, H) -> f` default to the Euclidean oracle's.
+    `objective(V, W, H) -> f` default to the Euclidean oracle's; kappa is
+    the projection fraction (0: rejection only).
 
     Returns (W, H, mm_evals, f, trace, accepted) with trace the objective at
     every QN iterate (trace[0] = f_0) and accepted the number of QN
@@ -116,6 +135,8 @@ def solve(V, W0, H0, q, max_mm, tol=None, tol_kind=nmf.GAP_NORMALIZED, check_eve
             Vs.pop(0)
         f2 = objective(V, W2, H2)
         xq = qn_step(np.stack(Us, axis=1), np.stack(Vs, axis=1), x, x1)
+        if xq is not None and kappa > 0.0:
+            xq = project(xq, x1, kappa)
         take = False
         if xq is not None and feasible(xq, x1):
             fq = objective(V, *_unpack(xq, p, r, n))

@@ -72,10 +72,11 @@ def test_fixed_point_is_preserved():
     rng = np.random.default_rng(6)
     Ws, Hs = rng.uniform(0.5, 1.5, size=(20, 3)), rng.uniform(0.5, 1.5, size=(3, 30))
     V = Ws @ Hs
-    W, H, evals, f, tr, acc = Q.solve(V, Ws, Hs, 4, 20)
-    assert acc == 0 and evals == 20
-    assert np.linalg.norm(W - Ws) <= 1e-13 * np.linalg.norm(Ws)
-    assert np.linalg.norm(H - Hs) <= 1e-13 * np.linalg.norm(Hs)
+    for kappa in (0.0, 0.5):
+        W, H, evals, f, tr, acc = Q.solve(V, Ws, Hs, 4, 20, kappa=kappa)
+        assert acc == 0 and evals == 20
+        assert np.linalg.norm(W - Ws) <= 1e-13 * np.linalg.norm(Ws)
+        assert np.linalg.norm(H - Hs) <= 1e-13 * np.linalg.norm(Hs)
 
 
 def test_monotone_safeguard():
@@ -101,12 +102,40 @@ def test_feasibility_reading():
 def test_fewer_map_evaluations_to_gap_on_the_small_workload():
     """256 x 512, rank 10 (uniform planted + noise): QN(4) reaches the gap
     f / ||V||^2 <= 3e-4 in fewer than 60% of plain MM's map evaluations
-    (measured: 126 against 342)."""
+    (measured: 126 against 342), in the rejection-only form (kappa = 0)."""
     V, W0, H0 = g.small_uniform()
     _, _, k_mm, f_mm, _ = O.solve(V, W0, H0, 5000, 3e-4, O.GAP_NORMALIZED, 1)
     W, H, k_qn, f_qn, tr, acc = Q.solve(V, W0, H0, 4, 5000, tol=3e-4,
-                                         tol_kind=O.GAP_NORMALIZED)
+                                         tol_kind=O.GAP_NORMALIZED, kappa=0.0)
     nv2 = float(np.sum(V.astype(np.float64) ** 2))
     assert f_qn / nv2 <= 3e-4 and f_mm / nv2 <= 3e-4
     assert k_qn < 0.6 * k_mm, (k_qn, k_mm)
     assert acc >= 1
+
+
+def test_projection_keeps_a_fraction_of_the_mm_point():
+    """max(x_qn, kappa F(x)): every entry at least kappa times its MM value,
+    hence feasible whenever F(x) >= 0; entries above the floor untouched."""
+    Fx = np.array([1.0, 0.0, 2.0, 4.0])
+    xq = np.array([-3.0, -1.0, 5.0, 1.0])
+    y = Q.project(xq, Fx, 0.5)
+    assert np.array_equal(y, [0.5, 0.0, 5.0, 2.0])
+    assert Q.feasible(y, Fx)
+
+
+def test_projected_qn_cuts_map_evaluations_on_sparse_matrices():
+    """A 512 x 1024 warm-start matrix (rank 24, sparse H): the rejection-only
+    form accepts almost no extrapolation, the projected form (kappa = 0.5)
+    reaches the 1e-4 gap in under half of plain MM's map evaluations
+    (measured 222 against 1822), monotonically."""
+    Wb = g.warm_start_base(p=512, r=24, seed=5000)
+    V = g.warm_start_matrix(Wb, 800, n=1024)[0]
+    W0, H0 = g.uniform_init(512, 1024, 24, seed=400800)
+    _, _, k_mm, _, _ = O.solve(V, W0, H0, 20000, 1e-4, O.GAP_NORMALIZED, 2)
+    _, _, k_qn, f, tr, acc = Q.solve(V, W0, H0, 4, 20000, tol=1e-4, check_every=1, kappa=0.5)
+    nv2 = float(np.sum(V.astype(np.float64) ** 2))
+    assert f / nv2 <= 1e-4
+    assert k_qn < 0.5 * k_mm, (k_qn, k_mm)
+    assert np.all(np.diff(tr) <= 1e-12 * np.abs(tr[1:]))
+    _, _, k0, _, _, acc0 = Q.solve(V, W0, H0, 4, 400, kappa=0.0)
+    assert acc0 <= 2
