@@ -574,7 +574,7 @@ def warm_start_experiment(args, log):
     net.close()
     net = infer
     runs = {"fp32_cold": [], "bf16_cold": [], "bf16_wbar": [], "bf16_net": [],
-            "bf16_hfit_ls": [], "bf16_net_ls": []}
+            "bf16_hfit_ls": [], "bf16_net_ls": [], "fp32_cold_qn": [], "bf16_net_ls_qn": []}
     for i, V in enumerate(test):
         m = 800 + i
         runs["fp32_cold"].append(ws.solve_to_gap(V, "cold", precision="fp32", seed=400000 + m,
@@ -586,6 +586,10 @@ def warm_start_experiment(args, log):
         runs["bf16_hfit_ls"].append(ws.solve_to_gap(V, "hfit_ls", precision="bf16", Wbar=Wbar))
         runs["bf16_net_ls"].append(ws.solve_to_gap(V, "net_ls", precision="bf16", Wbar=Wbar,
                                                    net=net))
+        runs["fp32_cold_qn"].append(ws.solve_to_gap(V, "cold", precision="fp32",
+                                                    seed=400000 + m, Wbar=Wbar, qn=4))
+        runs["bf16_net_ls_qn"].append(ws.solve_to_gap(V, "net_ls", precision="bf16", Wbar=Wbar,
+                                                      net=net, qn=4))
         log(f"test {m}: " + ", ".join(f"{k} {v[-1]['seconds']*1e3:.1f} ms / {v[-1]['iters']} it"
                                       for k, v in runs.items()))
     net.close()
@@ -593,6 +597,9 @@ def warm_start_experiment(args, log):
                "iters": int(np.median([x["iters"] for x in v])),
                "converged": int(sum(x["converged"] for x in v)),
                "gap_max": float(max(x["gap"] for x in v))} for k, v in runs.items()}
+    for k, v in runs.items():
+        if v and "qn_accepted" in v[0]:
+            med[k]["qn_accepted_median"] = int(np.median([x["qn_accepted"] for x in v]))
     return {
         "workload": "1024x4096 fp32 V_m = W_m H_m / max, W_m = W_base(1024x48, Gamma(2,0.5)) "
                     "* LogNormal(0,0.1), H_m sparse Exp; rank 48; gap f/||V||^2 <= 1e-4, "
@@ -612,6 +619,11 @@ def warm_start_experiment(args, log):
                                                     2),
         "network_gain_vs_wbar": round(med["bf16_wbar"]["ms"] / med["bf16_net"]["ms"], 2),
         "network_gain_vs_hfit_ls": round(med["bf16_hfit_ls"]["ms"] / med["bf16_net_ls"]["ms"], 2),
+        "qn": "QN(4) quasi-Newton acceleration (nmf_solve_qn): fp32_cold_qn from the FP32 cold "
+              "start, bf16_net_ls_qn from the warm start; iters = map evaluations",
+        "speedup_qn_fp32_cold": round(med["fp32_cold"]["ms"] / med["fp32_cold_qn"]["ms"], 2),
+        "speedup_qn_warm_vs_fp32_cold": round(med["fp32_cold"]["ms"] / med["bf16_net_ls_qn"]["ms"],
+                                              2),
         "train_loss": [round(x, 6) for x in losses],
         "pipeline_seconds": {"generate": round(t_gen, 1), "dictionary": round(t_dict, 1),
                              "targets": round(t_targets, 1), "train": round(t_train, 1),

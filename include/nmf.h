@@ -161,6 +161,31 @@ nmf_status nmf_objective(nmf_ctx* ctx, double* f_host);
 nmf_status nmf_solve(nmf_ctx* ctx, int32_t max_iters, int32_t* iters_done_host,
                      double* f_host, double* trace_host, int32_t trace_len);
 
+/* nmf_solve accelerated by the quasi-Newton scheme QN(q) of Zhou, Alexander
+   & Lange (2011), which the paper's Discussion cites (Tables 3 and 4,
+   columns QN(q)).  With F one iteration of Algorithm 1 on x = (W, H), each
+   QN iteration evaluates F twice, keeps the secant pairs u = F(x) - x,
+   v = F(F(x)) - F(x) of the last q QN iterations (U, V, float64), and forms
+     x_qn = F(x) + V (U^T U - U^T V)^-1 U^T u,
+   a Newton step for x = F(x) with the minimum-norm Jacobian approximation
+   satisfying the secant conditions.  x_qn is projected onto x >= 0.5 F(x)
+   (entrywise; NMF's iterates must stay positive, and the unprojected point
+   leaves the orthant almost every time on sparse data) and taken when the
+   q x q system is regular and f(x_qn) <= f(F(F(x))); otherwise the
+   iteration keeps F(F(x)).  So f never increases.  Every decision is made
+   on the device; one QN iteration is replayed from a HIP graph.
+   max_iters counts evaluations of F (two per QN iteration; at most 131072);
+   the stopping rule of the context's options is tested on the accepted
+   objective every check_every evaluations (check_every / 2 QN iterations,
+   at least one).  *iters_done_host: evaluations of F run; *accepted_host
+   (may be NULL): QN iterations whose extrapolated point was taken; *f_host:
+   the objective of the factors left in W and H; trace_host (may be NULL):
+   f_0 and then the objective after every QN iteration.  1 <= q <= 8.
+   NMF_EUNSUPPORTED for the Poisson loss.  Returns as nmf_solve. */
+nmf_status nmf_solve_qn(nmf_ctx* ctx, int32_t q, int32_t max_iters,
+                        int32_t* iters_done_host, int32_t* accepted_host,
+                        double* f_host, double* trace_host, int32_t trace_len);
+
 /* ||V||_F^2 in float64 (computed once by nmf_init); the normalizer of the
    NMF_TOL_GAP_NORMALIZED rule.  No device work. */
 nmf_status nmf_data_norm2(nmf_ctx* ctx, double* norm2_host);

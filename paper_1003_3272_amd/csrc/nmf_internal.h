@@ -197,6 +197,32 @@ hipError_t launch_kl_objective(int rp, const float* V, int64_t ldv, int64_t p, i
                                const float* Wp, const float* Hp, int64_t ldh, double* part,
                                hipStream_t st);
 
+// ---- QN(q) acceleration of the multiplicative map (x = [Wp | Hp]) --------
+int qn_max_q();      // largest q the kernels hold
+int qn_dot_blocks();  // rows of the dot-product partials (dpart: blocks x 3 q)
+// dst = src (D floats, D % 4 == 0).
+hipError_t launch_qn_copy(const float* src, float* dst, int64_t D, hipStream_t st);
+// Ring slot s = state[0] % q of U, V (float64, q x D): u = x1 - x0, v = x2 - x1.
+hipError_t launch_qn_pairs(const float* x0, const float* x1, const float* x2, double* U,
+                           double* V, int64_t D, int q, const int32_t* state, hipStream_t st);
+// Slot s's row / column of U^T U and U^T V (GUU, GUV: q_max x q_max), then
+// coef = (U^T U - U^T V)^-1 U^T u_s over the filled slots; state[2] = regular.
+hipError_t launch_qn_dots_solve(const double* U, const double* V, int64_t D, int q,
+                                int32_t* state, double* dpart, double* GUU, double* GUV,
+                                double* coef, hipStream_t st);
+// xq = max(x1 + V coef, kappa x1) (x1 if singular); state[3] |= infeasible.
+hipError_t launch_qn_combine(const float* x1, const double* V, const double* coef, int64_t D,
+                             int q, float kappa, int32_t* state, float* xq, hipStream_t st);
+// take = regular && feasible && fvals[1] <= fvals[0]; fout[state[0]] = the
+// accepted objective; state[0]++, state[1] += take.
+hipError_t launch_qn_select(const double* fvals, int32_t* state, double* fout, int32_t cap,
+                            hipStream_t st);
+// If taken: [Wp | Hp] = xq and its derived copies (caller's W and H; W^T in
+// float32, or bf16(W^T) and bf16(H)); pointers not used by the tier are null.
+hipError_t launch_qn_commit(const int32_t* state, const float* xq, float* Wp, int64_t ppad, int rp,
+                            int64_t npad, int64_t p, int r, int64_t n, float* Wc, float* Hc,
+                            float* WT, uint16_t* WbT, int64_t ldwt, uint16_t* Hb, hipStream_t st);
+
 // flag |= 1 if some V entry is negative or non-finite.
 hipError_t launch_validate(const float* V, int64_t ldv, int64_t p, int64_t n,
                            uint32_t* flag, hipStream_t st);

@@ -151,6 +151,17 @@ struct nmf_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gp[kGraphLevels] = {};
 
+  // QN(q) acceleration (allocated by the first nmf_solve_qn)
+  int qn_q = 0;
+  void* qn_ws = nullptr;
+  float *qx0 = nullptr, *qx1 = nullptr, *qxq = nullptr;
+  double *qU = nullptr, *qV = nullptr, *qdpart = nullptr, *qGUU = nullptr, *qGUV = nullptr;
+  double *qcoef = nullptr, *qf = nullptr;
+  int32_t* qst = nullptr;
+  double* qfout = nullptr;      // pinned, coherent: accepted objective per QN iteration
+  double* qfout_dev = nullptr;  // the same memory as the device addresses it
+  hipGraphExec_t qn_graph = nullptr;
+
   // stage profiler (HIP events on st)
   bool prof = false;
   int32_t prof_cap = 0;
@@ -346,6 +357,9 @@ nmf_status objective_sync(nmf_ctx* c, const float* Wp, double* f) {
 void free_ctx(nmf_ctx* c) {
   if (!c) return;
   profile_release(c);
+  if (c->qn_graph) (void)hipGraphExecDestroy(c->qn_graph);
+  if (c->qn_ws) (void)hipFree(c->qn_ws);
+  if (c->qfout) (void)hipHostFree(c->qfout);
   for (hipGraphExec_t g : c->gp)
     if (g) (void)hipGraphExecDestroy(g);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -380,6 +394,129 @@ nmf_status capture(nmf_ctx* c, int32_t iters, hipGraphExec_t* out) {
   const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   return ei == hipSuccess ? NMF_OK : NMF_EDEVICE;
+}
+
+constexpr int32_t kQnCap = 65536;  // QN iterations recorded per nmf_solve_qn call
+constexpr float kQnKappa = 0.5f;    // projection x >= kappa F(x) of the QN point
+
+int64_t qn_dim(const nmf_ctx* c) { return c->ppad * c->rp + (int64_t)c->rp * c->npad; }
+
+// Enqueue one QN(q) iteration (see nmf_qn.hip): two MM iterations with
+// snapshots, the secant pair, the q x q solve, the projected quasi-Newton
+// point, both objectives, the device-side choice and its commit, and the
+// Grams of the chosen factors for the next MM iteration.
+nmf_status qn_enqueue(nmf_ctx* c) {
+  const int64_t D = qn_dim(c);
+  const int q = c->qn_q;
+  TRY_HIP(launch_qn_copy(c->Wp, c->qx0, D, c->st));
+  TRY(iterate(c));
+  TRY_HIP(launch_qn_copy(c->Wp, c->qx1, D, c->st));
+  TRY(iterate(c));
+  TRY_HIP(launch_qn_pairs(c->qx0, c->qx1, c->Wp, c->qU, c->qV, D, q, c->qst, c->st));
+  TRY_HIP(launch_qn_dots_solve(c->qU, c->qV, D, q, c->qst, c->qdpart, c->qGUU, c->qGUV, c->qcoef,
+                               c->st));
+  TRY_HIP(launch_qn_combine(c->qx1, c->qV, c->qcoef, D, q, kQnKappa, c->qst, c->qxq, c->st));
+  TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, c->Wp, c->Hp, c->npad, c->fpart,
+                           c->st));
+  TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, c->qf + 0, c->st));
+  TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, c->qxq,
+                           c->qxq + c->ppad * c->rp, c->npad, c->fpart, c->st));
+  TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, c->qf + 1, c->st));
+  TRY_HIP(launch_qn_select(c->qf, c->qst, c->qfout_dev, kQnCap, c->st));
+  TRY_HIP(launch_qn_commit(c->qst, c->qxq, c->Wp, c->ppad, c->rp, c->npad, c->p, c->r, c->n,
+                           c->Wuser, c->Huser, c->bf16 ? nullptr : c->WT,
+                           c->bf16 ? c->WbT : nullptr, c->lwt, c->bf16 ? c->Hb : nullptr, c->st));
+  if (c->fuse) {
+    TRY_HIP(launch_update_w(c->rp, c->p, c->r, nullptr, 0, 0, 0, nullptr, c->Wp, c->Wuser,
+                            nullptr, nullptr, 0, c->bf16, c->gpw, c->uw_grid, c->uw_kpt, true,
+                            c->st));
+    TRY_HIP(launch_update_h(c->rp, c->n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, c->npad,
+                            c->Huser, nullptr, c->bf16, c->gph, c->uh_grid, c->uh_cols, true,
+                            c->st));
+  } else {
+    TRY(gram_h(c));
+    TRY(gram_w(c));
+  }
+  return NMF_OK;
+}
+
+// Workspace and graph of QN(q) for this context; the history (rings, their
+// Grams, counters) is cleared on every call.
+nmf_status qn_prepare(nmf_ctx* c, int q) {
+  const int64_t D = qn_dim(c);
+  const int qm = qn_max_q();
+  if (c->qn_q != q || !c->qn_ws) {
+    if (c->qn_graph) (void)hipGraphExecDestroy(c->qn_graph);
+    c->qn_graph = nullptr;
+    if (c->qn_ws) (void)hipFree(c->qn_ws);
+    c->qn_ws = nullptr;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      size_t o = off;
+      off += (bytes + 255) / 256 * 256;
+      return o;
+    };
+    const size_t ox0 = take(4 * (size_t)D), ox1 = take(4 * (size_t)D), oxq = take(4 * (size_t)D);
+    const size_t oU = take(8 * (size_t)q * D), oV = take(8 * (size_t)q * D);
+    const size_t odp = take(8 * (size_t)qn_dot_blocks() * 3 * q);
+    const size_t oguu = take(8 * (size_t)qm * qm), oguv = take(8 * (size_t)qm * qm);
+    const size_t oc = take(8 * (size_t)qm), of = take(8 * 2), ost = take(4 * 8);
+    if (hipMalloc(&c->qn_ws, off) != hipSuccess) {
+      c->qn_ws = nullptr;
+      (void)hipGetLastError();
+      return NMF_ENOMEM;
+    }
+    char* b = static_cast<char*>(c->qn_ws);
+    c->qx0 = reinterpret_cast<float*>(b + ox0);
+    c->qx1 = reinterpret_cast<float*>(b + ox1);
+    c->qxq = reinterpret_cast<float*>(b + oxq);
+    c->qU = reinterpret_cast<double*>(b + oU);
+    c->qV = reinterpret_cast<double*>(b + oV);
+    c->qdpart = reinterpret_cast<double*>(b + odp);
+    c->qGUU = reinterpret_cast<double*>(b + oguu);
+    c->qGUV = reinterpret_cast<double*>(b + oguv);
+    c->qcoef = reinterpret_cast<double*>(b + oc);
+    c->qf = reinterpret_cast<double*>(b + of);
+    c->qst = reinterpret_cast<int32_t*>(b + ost);
+    c->qn_q = q;
+    if (!c->qfout) {
+      if (hipHostMalloc(reinterpret_cast<void**>(&c->qfout), sizeof(double) * kQnCap,
+                        hipHostMallocCoherent) != hipSuccess) {
+        c->qfout = nullptr;
+        (void)hipGetLastError();
+        return NMF_ENOMEM;
+      }
+      TRY_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->qfout_dev), c->qfout, 0));
+    }
+    // one QN iteration as a graph (arguments fixed; per-iteration indices
+    // live in device memory)
+    if (!c->cap_stream) TRY_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->st;
+    const bool prof = c->prof;
+    c->prof = false;
+    c->st = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    nmf_status s = NMF_OK;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      s = NMF_EDEVICE;
+    if (s == NMF_OK) {
+      s = qn_enqueue(c);
+      const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+      if (s == NMF_OK && (e != hipSuccess || !graph)) s = NMF_EDEVICE;
+    }
+    c->st = user;
+    c->prof = prof;
+    if (s == NMF_OK &&
+        hipGraphInstantiate(&c->qn_graph, graph, nullptr, nullptr, 0) != hipSuccess)
+      s = NMF_EDEVICE;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (s != NMF_OK) return s;
+  }
+  // clear the history: rings, Grams, coefficients, counters (fill kernels)
+  const size_t words = ((size_t)(reinterpret_cast<char*>(c->qst) - reinterpret_cast<char*>(c->qU)) +
+                        4 * 8) / 4;
+  TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(c->qU), (int64_t)words, 0u, c->st));
+  return NMF_OK;
 }
 
 nmf_status setup(nmf_ctx* c) {
@@ -788,6 +925,60 @@ nmf_status nmf_solve(nmf_ctx* c, int32_t max_iters, int32_t* iters_done, double*
     f_prev = f;
   }
   if (s == NMF_ENONFINITE) return s;
+  return done ? NMF_OK : NMF_ENOTCONVERGED;
+}
+
+nmf_status nmf_solve_qn(nmf_ctx* c, int32_t q, int32_t max_iters, int32_t* iters_done,
+                        int32_t* accepted, double* f_host, double* trace, int32_t trace_len) {
+  if (!c || !iters_done || !f_host || q < 1 || max_iters < 0) return NMF_EINVAL;
+  if (trace && trace_len < 0) return NMF_EINVAL;
+  if (q > qn_max_q() || max_iters / 2 > kQnCap) return NMF_EINVAL;
+  if (c->kl) return NMF_EUNSUPPORTED;
+  if (c->Hp != c->Wp + c->ppad * c->rp) return NMF_EUNSUPPORTED;  // [Wp | Hp] contiguous
+  *iters_done = 0;
+  if (accepted) *accepted = 0;
+  double f_prev;
+  nmf_status s = nmf_objective(c, &f_prev);
+  *f_host = f_prev;
+  if (s != NMF_OK) return s;
+  int32_t nt = 0;
+  if (trace && nt < trace_len) trace[nt++] = f_prev;
+  TRY(qn_prepare(c, q));
+  // chunks of check_every map evaluations (check_every / 2 QN iterations,
+  // at least one); the rule is tested on the accepted objective at the end
+  // of each chunk
+  const int32_t chunk = std::max<int32_t>(1, c->opt.check_every / 2);
+  const int32_t total = max_iters / 2;
+  int32_t it = 0;
+  bool done = false;
+  double f = f_prev;
+  while (!done && it < total) {
+    const int32_t todo = std::min(chunk, total - it);
+    for (int32_t k = 0; k < todo; ++k) TRY_HIP(hipGraphLaunch(c->qn_graph, c->st));
+    TRY_HIP(hipStreamSynchronize(c->st));
+    for (int32_t k = it; k < it + todo; ++k)
+      if (trace && nt < trace_len) trace[nt++] = c->qfout[k];
+    it += todo;
+    f = c->qfout[it - 1];
+    if (!std::isfinite(f)) {
+      s = NMF_ENONFINITE;
+      break;
+    }
+    if (c->opt.tol_kind == NMF_TOL_REL_CHANGE)
+      done = std::fabs(f - f_prev) / (std::fabs(f_prev) + 1.0) < c->opt.tol;
+    else
+      done = (c->nv2 > 0.0 ? f / c->nv2 : 0.0) <= c->opt.tol;
+    f_prev = f;
+  }
+  *iters_done = 2 * it;
+  *f_host = f;
+  if (accepted) {
+    int32_t* st = reinterpret_cast<int32_t*>(c->hostbuf);  // pinned
+    TRY_HIP(hipMemcpyAsync(st, c->qst, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    TRY_HIP(hipStreamSynchronize(c->st));
+    *accepted = st[1];
+  }
+  if (s != NMF_OK) return s;
   return done ? NMF_OK : NMF_ENOTCONVERGED;
 }
 

@@ -93,6 +93,9 @@ def load(path: str = LIB_PATH):
     lib.nmf_solve.argtypes = [P, c_int32, POINTER(c_int32), POINTER(c_double),
                               POINTER(c_double), c_int32]
     lib.nmf_solve.restype = c_int32
+    lib.nmf_solve_qn.argtypes = [P, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                 POINTER(c_double), POINTER(c_double), c_int32]
+    lib.nmf_solve_qn.restype = c_int32
     lib.nmf_refit_w.argtypes = [P, ctypes.c_float]
     lib.nmf_refit_w.restype = c_int32
     lib.nmf_data_norm2.argtypes = [P, POINTER(c_double)]
@@ -276,6 +279,17 @@ class Nmf:
             ce = self.opts.check_every
             ntr = min(trace_len, 1 + (it.value + ce - 1) // ce)
         return st == NMF_OK, it.value, f.value, [buf[i] for i in range(ntr)]
+
+    def solve_qn(self, max_iters: int, q: int = 4, trace_len: int = 0):
+        """QN(q)-accelerated solve (nmf_solve_qn).  Returns (converged,
+        map evaluations, accepted QN steps, f, trace list)."""
+        it, acc, f = c_int32(), c_int32(), c_double()
+        buf = (c_double * max(trace_len, 1))()
+        st = load().nmf_solve_qn(self._ctx, int(q), int(max_iters), byref(it), byref(acc),
+                                 byref(f), buf if trace_len > 0 else None, int(trace_len))
+        self._check(st, "nmf_solve_qn")
+        ntr = min(trace_len, 1 + it.value // 2) if trace_len > 0 else 0
+        return st == NMF_OK, it.value, acc.value, f.value, [buf[i] for i in range(ntr)]
 
     def refit_w(self, floor_rel: float = 1e-3):
         """W <- max(V H^T (H H^T + delta I)^-1, floor_rel * max W): the

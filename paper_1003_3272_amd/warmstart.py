@@ -119,7 +119,7 @@ def train(net, Vs, Hs, epochs, lr, batch=512, decay=0.9, seed=0, log=None):
 
 
 def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters=20000,
-                 net=None, Wbar=None, seed=None, ls_floor=1e-3, hfit=20):
+                 net=None, Wbar=None, seed=None, ls_floor=1e-3, hfit=20, qn=0):
     """Time to reach f / ||V||_F^2 <= tol from a given start (V already on
     the device).  start: "cold" (device U(0,1) draw keyed by `seed`),
     "wbar" (W-bar and a constant H), "net" (nmf_ws_predict: the network's
@@ -127,6 +127,9 @@ def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters
     "net_ls" (H0 = net(V), W0 refit to H0 by least squares) or "hfit_ls"
     (no network: H fitted to W-bar by `hfit` H-only multiplicative updates
     from a constant H, then W0 refit to that H).
+    qn > 0 refines with the QN(qn)-accelerated solver (nmf_solve_qn)
+    instead of plain multiplicative updates; iterations then count map
+    evaluations (two per QN iteration).
     The clock covers everything after V is resident: the start, context
     set-up (casts, copies), every iteration and every objective check.
     Returns a dict with seconds, iterations, final gap and convergence."""
@@ -157,9 +160,16 @@ def solve_to_gap(V, start, tol=1e-4, precision="fp32", check_every=10, max_iters
                 ctx.update_h()
         if start in ("net_ls", "hfit_ls"):
             ctx.refit_w(ls_floor)
-    conv, iters, f, _ = ctx.solve(max_iters)
+    accepted = None
+    if qn > 0:
+        conv, iters, accepted, f, _ = ctx.solve_qn(max_iters, q=qn)
+    else:
+        conv, iters, f, _ = ctx.solve(max_iters)
     _sync()
     seconds = time.perf_counter() - t0
     gap = f / ctx.data_norm2()
     ctx.close()
-    return {"seconds": seconds, "iters": iters, "gap": gap, "converged": bool(conv)}
+    out = {"seconds": seconds, "iters": iters, "gap": gap, "converged": bool(conv)}
+    if accepted is not None:
+        out["qn_accepted"] = accepted
+    return out
