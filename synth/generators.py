@@ -142,3 +142,60 @@ def mlp_init(p, d, r, seed):
     M1 = rng.uniform(-a1, a1, size=(d, p)).astype(np.float32)
     M2 = rng.uniform(-a2, a2, size=(r, d)).astype(np.float32)
     return [M1, np.zeros(d, np.float32), M2, np.zeros(r, np.float32)]
+
+
+# PET (the paper's second demonstration, Sec. 3.2) ----------------------------
+def pet_geometry(grid=64, detectors=64, step=0.05):
+    """System matrix of a ring of `detectors` detectors around a grid x grid
+    image: one line of flight per detector pair (64 detectors: 2016 lines),
+    e_ij = length of line i inside pixel j (unit pixels, image centred on the
+    ring's centre, ring radius = 1.05 x the image's half diagonal), measured
+    by sampling each chord every `step` pixels.  Returns E (d x p, float32,
+    row-major, pixels in row-major order)."""
+    rad = 1.05 * grid / np.sqrt(2.0)
+    ang = 2.0 * np.pi * np.arange(detectors) / detectors
+    pts = np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
+    pairs = [(a, b) for a in range(detectors) for b in range(a + 1, detectors)]
+    E = np.zeros((len(pairs), grid * grid), dtype=np.float64)
+    for i, (a, b) in enumerate(pairs):
+        p0, p1 = pts[a], pts[b]
+        L = float(np.linalg.norm(p1 - p0))
+        m = int(np.ceil(L / step))
+        t = (np.arange(m) + 0.5) / m
+        xy = p0[None, :] + t[:, None] * (p1 - p0)[None, :]
+        col = np.floor(xy[:, 0] + grid / 2).astype(np.int64)
+        row = np.floor(grid / 2 - xy[:, 1]).astype(np.int64)
+        ok = (col >= 0) & (col < grid) & (row >= 0) & (row < grid)
+        np.add.at(E[i], row[ok] * grid + col[ok], L / m)
+    return E.astype(np.float32)
+
+
+def pet_phantom(grid=64):
+    """Emission intensities of a synthetic phantom (grid x grid, row-major):
+    a disc of intensity 1 with two hot ellipses (4 and 2.5) and a cold one
+    (0.2)."""
+    yy, xx = np.mgrid[0:grid, 0:grid]
+    x = (xx + 0.5) / grid * 2.0 - 1.0
+    y = 1.0 - (yy + 0.5) / grid * 2.0
+    lam = np.where(x ** 2 + y ** 2 <= 0.85 ** 2, 1.0, 0.0)
+    for cx, cy, ax, ay, v in ((-0.3, 0.25, 0.18, 0.12, 4.0), (0.35, -0.2, 0.1, 0.2, 2.5),
+                              (0.1, 0.45, 0.12, 0.08, 0.2)):
+        lam = np.where(((x - cx) / ax) ** 2 + ((y - cy) / ay) ** 2 <= 1.0, v, lam)
+    return lam.ravel()
+
+
+def pet_counts(E, lam, mean_count=50.0, seed=6000):
+    """Coincidence counts y_i ~ Poisson(s (E lam)_i) with s chosen so that the
+    mean count per line is mean_count (float32 holding integers)."""
+    rng = np.random.default_rng(seed)
+    mu = np.asarray(E, np.float64) @ np.asarray(lam, np.float64)
+    s = mean_count / max(float(mu.mean()), 1e-300)
+    return rng.poisson(s * mu).astype(np.float32)
+
+
+def pet_problem(grid=64, detectors=64, seed=6000):
+    """(E, y, true intensities): the 64 x 64 image interrogated by 2016 lines
+    of flight (the paper's PET problem size)."""
+    E = pet_geometry(grid, detectors)
+    lam = pet_phantom(grid)
+    return E, pet_counts(E, lam, seed=seed), lam
