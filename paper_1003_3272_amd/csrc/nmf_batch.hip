@@ -1060,7 +1060,8 @@ nmf_status capture(nmf_batch* b, int32_t iters) {
   (void)hipGraphDestroy(graph);
   if (ei != hipSuccess) return NMF_EDEVICE;
   b->graph_iters = iters;
-  return NMF_OK;
+  // upload now, so that the first launch costs what every later one does
+  return hipGraphUpload(b->graph, b->st) == hipSuccess ? NMF_OK : NMF_EDEVICE;
 }
 
 // Synchronize; NMF_EDEVICE if a launch since the last check hit the wait

@@ -393,7 +393,9 @@ nmf_status capture(nmf_ctx* c, int32_t iters, hipGraphExec_t* out) {
   if (e != hipSuccess || !graph) return NMF_EDEVICE;
   const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
-  return ei == hipSuccess ? NMF_OK : NMF_EDEVICE;
+  if (ei != hipSuccess) return NMF_EDEVICE;
+  // upload now, so that the first launch costs what every later one does
+  return hipGraphUpload(*out, c->st) == hipSuccess ? NMF_OK : NMF_EDEVICE;
 }
 
 constexpr int32_t kQnCap = 65536;  // QN iterations recorded per nmf_solve_qn call
@@ -507,7 +509,8 @@ nmf_status qn_prepare(nmf_ctx* c, int q) {
     c->st = user;
     c->prof = prof;
     if (s == NMF_OK &&
-        hipGraphInstantiate(&c->qn_graph, graph, nullptr, nullptr, 0) != hipSuccess)
+        (hipGraphInstantiate(&c->qn_graph, graph, nullptr, nullptr, 0) != hipSuccess ||
+         hipGraphUpload(c->qn_graph, c->st) != hipSuccess))
       s = NMF_EDEVICE;
     if (graph) (void)hipGraphDestroy(graph);
     if (s != NMF_OK) return s;

@@ -549,6 +549,19 @@ class Batch:
         t = (c_int32 * BATCH_TABLE_LEN)(*[int(v) for v in values])
         self._check(load().nmf_batch_set_table(self._b, t), "nmf_batch_set_table")
 
+    def save_table(self, path):
+        """Write the installed tile table to a JSON file (to install it again
+        with load_table instead of re-tuning)."""
+        import json
+        with open(path, "w") as fh:
+            json.dump({"nmf_batch_table": self.table}, fh)
+
+    def load_table(self, path):
+        """Install a tile table written by save_table."""
+        import json
+        with open(path) as fh:
+            self.table = json.load(fh)["nmf_batch_table"]
+
     def tune(self, trial_iters=5):
         """Autotune the tile table on this batch; returns ms per iteration of
         the table it installs."""
@@ -572,3 +585,4 @@ class Batch:
             self.close()
         except Exception:
             pass
+

@@ -344,3 +344,23 @@ def test_queue_modes_agree(gpu_lib, reference, monkeypatch):
     for (_, W, H), (_, W2, H2) in zip(out[0], out[1]):
         assert torch.equal(W, W2) and torch.equal(H, H2)
     _check_10(out[0], ref, "local")
+
+
+def test_tile_table_persists(gpu_lib, reference, tmp_path):
+    """A tuned table written by save_table and installed by load_table in a
+    new batch gives the same results as the tuned batch itself."""
+    from paper_1003_3272_amd import nmf
+    host, _ = reference
+    dev1, dev2 = _device(host), _device(host)
+    path = tmp_path / "table.json"
+    with nmf.Batch(dev1) as b:
+        b.tune(trial_iters=2)
+        b.save_table(path)
+        b.step(7)
+        t1 = b.table
+    with nmf.Batch(dev2) as b:
+        b.load_table(path)
+        assert b.table == t1
+        b.step(7)
+    for (_, W, H), (_, W2, H2) in zip(dev1, dev2):
+        assert torch.equal(W, W2) and torch.equal(H, H2)
