@@ -419,6 +419,51 @@ nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count,
                            int32_t max_iters, const nmf_options* opt,
                            int32_t* iters_done_host, double* f_out, void* stream);
 
+/* ---- Penalized PET reconstruction (Sec. 3.2, Algorithm 2) ----------------
+   The paper's second MM demonstration, with the same separation of
+   parameters: Poisson emission intensities lambda (p pixels on a rows x cols
+   grid, row-major) seen through d lines of flight with geometry E (d x p)
+   and counts y (d), maximizing the penalized log-likelihood (eq.
+   PET-objpen)
+     f(lambda) = sum_i [y_i ln (E lambda)_i - (E lambda)_i]
+                 - (mu / 2) sum_{{j,k} adjacent} (lambda_j - lambda_k)^2
+   over the 4-neighbour pairs of the grid.  Algorithm 2: E is scaled to unit
+   column sums (on the device, at creation); each iteration forms, for all
+   pixels in parallel, c_j = lambda_j sum_i e_ij y_i / (E lambda)_i,
+   b_j = mu (|N_j| lambda_j + sum_{k in N_j} lambda_k) - 1, a_j = -2 mu |N_j|
+   and takes the positive root of a_j x^2 + b_j x + c_j = 0 (evaluated as
+   2 c / (-b + sqrt(b^2 - 4 a c)) when b <= 0, the same root without the
+   printed form's cancellation at small mu, and in the printed form when
+   b > 0; mu = 0 gives the EM update c_j).  The text's
+   formula for b omits the factor mu that Algorithm 2 and the derivative
+   carry; b includes it.  float32 products, float64 objective. */
+typedef struct nmf_pet nmf_pet;
+
+/* E (d x p row-major), y (d) and lambda (p) are device pointers, 16-byte
+   aligned; p = rows * cols, a multiple of 4; mu >= 0.  E and y are copied
+   (E scaled) at creation; lambda is the caller's start (Algorithm 2 uses
+   all ones), updated in place by every step, and must outlive the object.
+   Errors: NMF_EINVAL, NMF_EUNSUPPORTED (p not a multiple of 4), NMF_ENOMEM. */
+nmf_status nmf_pet_create(nmf_pet** out, const float* E, int64_t d, int64_t p,
+                          const float* y, int32_t rows, int32_t cols, double mu,
+                          float* lambda, void* stream);
+
+/* Enqueue `iters` iterations (replayed from HIP graphs of 16, 8, 4, 2 and 1
+   iterations).  Asynchronous. */
+nmf_status nmf_pet_step(nmf_pet* m, int32_t iters);
+
+/* f(lambda) of the current intensities in float64; synchronizes. */
+nmf_status nmf_pet_objective(nmf_pet* m, double* f_host);
+
+/* Iterate until |f_k - f_prev| / (|f_prev| + 1) < tol at a check (every
+   check_every iterations; the stopping rule of Sec. 3) or max_iters.
+   Returns NMF_OK, NMF_ENOTCONVERGED at the cap, NMF_ENONFINITE. */
+nmf_status nmf_pet_solve(nmf_pet* m, int32_t max_iters, double tol, int32_t check_every,
+                         int32_t* iters_done_host, double* f_host);
+
+/* Release the object (not the caller's lambda).  NULL is ignored. */
+void nmf_pet_destroy(nmf_pet* m);
+
 /* Release the context's workspace.  NULL is ignored. */
 void nmf_destroy(nmf_ctx* ctx);
 

@@ -152,6 +152,18 @@ def load(path: str = LIB_PATH):
     lib.nmf_batch_solve.argtypes = [POINTER(NmfProblem), c_int32, c_int32, POINTER(NmfOptions),
                                      POINTER(c_int32), POINTER(c_double), P]
     lib.nmf_batch_solve.restype = c_int32
+    lib.nmf_pet_create.argtypes = [POINTER(P), P, c_int64, c_int64, P, c_int32, c_int32, c_double,
+                                   P, P]
+    lib.nmf_pet_create.restype = c_int32
+    lib.nmf_pet_step.argtypes = [P, c_int32]
+    lib.nmf_pet_step.restype = c_int32
+    lib.nmf_pet_objective.argtypes = [P, POINTER(c_double)]
+    lib.nmf_pet_objective.restype = c_int32
+    lib.nmf_pet_solve.argtypes = [P, c_int32, c_double, c_int32, POINTER(c_int32),
+                                  POINTER(c_double)]
+    lib.nmf_pet_solve.restype = c_int32
+    lib.nmf_pet_destroy.argtypes = [P]
+    lib.nmf_pet_destroy.restype = None
     lib.nmf_strerror.argtypes = [c_int32]
     lib.nmf_strerror.restype = ctypes.c_char_p
     lib.nmf_version.argtypes = []
@@ -586,3 +598,63 @@ class Batch:
         except Exception:
             pass
 
+
+class Pet:
+    """Penalized PET reconstruction (Algorithm 2) on the GPU: E (d, p) and
+    y (d,) float32 CUDA tensors, lam (p,) float32 CUDA tensor updated in
+    place, p = rows * cols pixels in row-major order."""
+
+    def __init__(self, E, y, lam, rows, cols, mu, stream=None):
+        import torch
+        for name, t in (("E", E), ("y", y), ("lam", lam)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+                    or not t.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+        d, p = E.shape
+        if y.shape != (d,) or lam.shape != (p,):
+            raise ValueError("shapes: E (d, p), y (d,), lam (p,)")
+        self._keep = (E, y, lam)
+        self._m = c_void_p()
+        st = load().nmf_pet_create(byref(self._m), _ptr(E), d, p, _ptr(y), int(rows), int(cols),
+                                   float(mu), _ptr(lam), _stream_handle(stream))
+        if st != NMF_OK:
+            self._m = c_void_p()
+            raise NmfError(st, "nmf_pet_create")
+
+    def _check(self, st, what):
+        if st not in (NMF_OK, NMF_ENOTCONVERGED):
+            raise NmfError(st, what)
+        return st
+
+    def step(self, iters=1):
+        self._check(load().nmf_pet_step(self._m, int(iters)), "nmf_pet_step")
+
+    def objective(self):
+        f = c_double()
+        self._check(load().nmf_pet_objective(self._m, byref(f)), "nmf_pet_objective")
+        return f.value
+
+    def solve(self, max_iters, tol=1e-9, check_every=1):
+        """Returns (converged, iterations, f)."""
+        it, f = c_int32(), c_double()
+        st = self._check(load().nmf_pet_solve(self._m, int(max_iters), float(tol),
+                                              int(check_every), byref(it), byref(f)),
+                         "nmf_pet_solve")
+        return st == NMF_OK, it.value, f.value
+
+    def close(self):
+        if self._m:
+            load().nmf_pet_destroy(self._m)
+            self._m = c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

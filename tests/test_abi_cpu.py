@@ -205,3 +205,27 @@ def test_poisson_loss_rejects_options_it_does_not_offer(kw):
     o = nmf.options(loss="poisson", **kw)
     st, _ = _init(opt=o, r=r)
     assert st == nmf.NMF_EUNSUPPORTED
+
+
+def test_pet_calls_reject_bad_arguments_before_device_work():
+    lib = nmf.load()
+    out = ctypes.c_void_p()
+    P = ctypes.byref(out)
+    # (E, d, p, y, rows, cols, mu, lambda): rows * cols must be p, mu >= 0,
+    # pointers non-null and 16-byte aligned, p a multiple of 4
+    ok = (FAKE, 10, 12, FAKE, 3, 4, 0.1, FAKE)
+    cases = [((None,) + ok[1:], nmf.NMF_EINVAL), (ok[:1] + (0,) + ok[2:], nmf.NMF_EINVAL),
+             (ok[:4] + (4, 4) + ok[6:], nmf.NMF_EINVAL), (ok[:6] + (-1.0, FAKE), nmf.NMF_EINVAL),
+             (ok[:6] + (float("nan"), FAKE), nmf.NMF_EINVAL),
+             (ok[:7] + (FAKE + 4,), nmf.NMF_EINVAL),
+             ((FAKE, 10, 10, FAKE, 2, 5, 0.1, FAKE), nmf.NMF_EUNSUPPORTED)]
+    for args, code in cases:
+        assert lib.nmf_pet_create(P, *args, None) == code, args
+        assert not out.value
+    assert lib.nmf_pet_create(None, *ok, None) == nmf.NMF_EINVAL
+    f, it = ctypes.c_double(), ctypes.c_int32()
+    assert lib.nmf_pet_step(None, 1) == nmf.NMF_EINVAL
+    assert lib.nmf_pet_objective(None, ctypes.byref(f)) == nmf.NMF_EINVAL
+    assert lib.nmf_pet_solve(None, 10, 1e-9, 1, ctypes.byref(it), ctypes.byref(f)) == \
+        nmf.NMF_EINVAL
+    lib.nmf_pet_destroy(None)

@@ -1,0 +1,160 @@
+"""GPU parity of the penalized PET reconstruction MM algorithm (Sec. 3.2,
+Algorithm 2) against the float64 oracle oracle/pet_oracle.py, on the same
+float32 inputs, through the C ABI (nmf_pet_*).
+
+Workloads: the 64 x 64 image seen by 2016 lines of flight of a 64-detector
+ring (the paper's problem size, synthetic geometry and phantom), and a small
+ragged problem (37 lines, 9 x 12 grid, a pixel that no line crosses, lines
+with zero counts) that exercises the padding and the b > 0 branch of the
+root.
+
+Bars (float32 products against float64): f within 1e-5 relative at each of
+the first 20 iterations and lambda within 1e-4 relative (Frobenius) after
+20; f non-decreasing (float32 slack 1e-6 |f|); bit-identical intensities for
+every split of the iterations over the replayed graphs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pet_oracle as O
+from synth import generators as g
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full_problem():
+    E, y, _ = g.pet_problem()
+    return E, y, 64, 64
+
+
+def _ragged_problem():
+    rng = np.random.default_rng(6100)
+    rows, cols, d = 9, 12, 37
+    p = rows * cols
+    E = rng.exponential(1.0, size=(d, p)) * (rng.uniform(size=(d, p)) < 0.2)
+    E[:, 50] = 0.0                                   # a pixel no line crosses
+    lam_true = rng.gamma(2.0, 2.0, size=p)
+    y = rng.poisson(E @ lam_true).astype(np.float64)
+    y[::5] = 0.0                                     # lines with zero counts
+    return E.astype(np.float32), y.astype(np.float32), rows, cols
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _gpu_run(E, y, rows, cols, mu, iters, lam0=None, each=True):
+    from paper_1003_3272_amd import nmf
+    p = E.shape[1]
+    lam0 = np.ones(p, np.float32) if lam0 is None else lam0
+    Ed, yd, ld = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (E, y, lam0))
+    trace = []
+    with nmf.Pet(Ed, yd, ld, rows, cols, mu) as m:
+        trace.append(m.objective())
+        if each:
+            for _ in range(iters):
+                m.step(1)
+                trace.append(m.objective())
+        else:
+            m.step(iters)
+            trace.append(m.objective())
+    return ld.cpu().numpy(), np.array(trace)
+
+
+@pytest.mark.parametrize("mu", [0.0, 1e-5, 1e-3, 1e-1])
+def test_pet_matches_oracle_full_size(gpu_lib, full_problem, mu):
+    E, y, rows, cols = full_problem
+    pairs = O.neighbour_pairs(rows, cols)
+    lam, tr = _gpu_run(E, y, rows, cols, mu, 20)
+    lam_o, tr_o = O.run(E, y, np.ones(E.shape[1]), mu, pairs, 20)
+    err = np.abs(tr - tr_o) / np.abs(tr_o)
+    assert err.max() < 1e-5, (mu, err.max(), int(err.argmax()))
+    assert rel(lam, lam_o) < 1e-4
+    assert (lam >= 0).all()
+
+
+@pytest.mark.parametrize("mu", [0.0, 1e-2, 1.0])
+def test_pet_matches_oracle_ragged(gpu_lib, mu):
+    E, y, rows, cols = _ragged_problem()
+    pairs = O.neighbour_pairs(rows, cols)
+    lam, tr = _gpu_run(E, y, rows, cols, mu, 20)
+    lam_o, tr_o = O.run(E, y, np.ones(E.shape[1]), mu, pairs, 20)
+    err = np.abs(tr - tr_o) / np.maximum(np.abs(tr_o), 1.0)
+    assert err.max() < 1e-5, (mu, err.max())
+    assert rel(lam, lam_o) < 1e-4
+    # the uncrossed pixel has c = 0: it is 0 while b <= 0 and -b / a once
+    # its neighbours make b positive (at mu = 1, from the first iteration)
+    assert abs(lam[50] - lam_o[50]) <= 1e-4 * lam_o.max()
+    if mu >= 1.0:
+        assert lam_o[50] > 0
+    if mu == 0.0:
+        assert lam[50] == 0.0
+
+
+def test_pet_tiny_penalty_root_is_stable(gpu_lib, full_problem):
+    """At mu = 1e-9 the printed root form cancels in float32; the kernel's
+    form must still track the float64 oracle (whose own cancellation costs
+    about 1e-9 relative here)."""
+    E, y, rows, cols = full_problem
+    pairs = O.neighbour_pairs(rows, cols)
+    lam, _ = _gpu_run(E, y, rows, cols, 1e-9, 5, each=False)
+    lam_o, _ = O.run(E, y, np.ones(E.shape[1]), 1e-9, pairs, 5)
+    assert rel(lam, lam_o) < 1e-5
+
+
+@pytest.mark.parametrize("mu", [0.0, 1e-3])
+def test_pet_objective_ascends(gpu_lib, full_problem, mu):
+    from paper_1003_3272_amd import nmf
+    E, y, rows, cols = full_problem
+    Ed, yd = torch.from_numpy(E).cuda(), torch.from_numpy(y).cuda()
+    ld = torch.ones(E.shape[1], dtype=torch.float32, device="cuda")
+    with nmf.Pet(Ed, yd, ld, rows, cols, mu) as m:
+        fs = [m.objective()]
+        for _ in range(40):
+            m.step(7)
+            fs.append(m.objective())
+    fs = np.array(fs)
+    slack = 1e-6 * np.abs(fs[1:])
+    assert (np.diff(fs) >= -slack).all(), np.diff(fs).min()
+    assert fs[-1] > fs[0]
+
+
+def test_pet_graph_splits_are_bit_identical(gpu_lib, full_problem):
+    E, y, rows, cols = full_problem
+    a, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=False)      # 16 + 4 + 2 + 1
+    b, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=True)       # 23 x 1
+    c, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=False)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_pet_solve_stopping_rule(gpu_lib, full_problem):
+    from paper_1003_3272_amd import nmf
+    E, y, rows, cols = full_problem
+    pairs = O.neighbour_pairs(rows, cols)
+    Ed, yd = torch.from_numpy(E).cuda(), torch.from_numpy(y).cuda()
+    ld = torch.ones(E.shape[1], dtype=torch.float32, device="cuda")
+    with nmf.Pet(Ed, yd, ld, rows, cols, 1e-2) as m:
+        conv, it, f = m.solve(5, tol=0.0)
+        assert not conv and it == 5
+        conv, it, f = m.solve(20000, tol=1e-7, check_every=4)
+        assert conv and 0 < it < 20000 and it % 4 == 0
+        assert f == m.objective()
+        f_next = (m.step(4), m.objective())[1]
+        assert abs(f_next - f) / (abs(f) + 1.0) < 1e-6
+    lam = ld.cpu().numpy()
+    fo = O.objective(O.scale_columns(E), y, lam, 1e-2, pairs)
+    assert abs(fo - f_next) <= 1e-6 * abs(fo)
+
+
+def test_pet_start_is_the_callers(gpu_lib):
+    """lambda is the caller's buffer: a non-uniform start is used as given
+    and updated in place."""
+    E, y, rows, cols = _ragged_problem()
+    lam0 = np.random.default_rng(6101).uniform(0.5, 2.0, size=E.shape[1]).astype(np.float32)
+    pairs = O.neighbour_pairs(rows, cols)
+    lam, tr = _gpu_run(E, y, rows, cols, 1e-2, 3, lam0=lam0)
+    lam_o, tr_o = O.run(E, y, lam0, 1e-2, pairs, 3)
+    assert abs(tr[0] - tr_o[0]) <= 1e-6 * max(abs(tr_o[0]), 1.0)
+    assert rel(lam, lam_o) < 1e-5
