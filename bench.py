@@ -73,6 +73,10 @@ def parse():
     ap.add_argument("--no-poisson", action="store_true",
                     help="skip the Poisson (KL) update at the headline shape")
     ap.add_argument("--poisson-ranks", type=int, nargs="+", default=[64, 32])
+    ap.add_argument("--no-pet", action="store_true",
+                    help="skip the penalized PET reconstruction runs")
+    ap.add_argument("--pet-mus", type=float, nargs="+", default=[0.0, 1e-7, 1e-6, 1e-5])
+    ap.add_argument("--pet-max-iters", type=int, default=100000)
     ap.add_argument("--pt-iters", type=int, default=200)
     ap.add_argument("--pt-ranks", type=int, nargs="+", default=[32, 128, 256])
     ap.add_argument("--pmc-calibration", action="store_true",
@@ -348,6 +352,74 @@ def poisson_experiment(Vd, args, log):
         log(f"poisson r={r}: {out['ranks'][str(r)]['iters_per_s']} it/s, pass {ms * 1e3:.1f} us "
             f"({roof['frac']} of FP32 MFMA)")
         del Wd, Hd
+    return out
+
+
+def pet_experiment(args, log):
+    """Penalized PET reconstruction (Algorithm 2) at the paper's problem size:
+    a 64 x 64 image, 2016 lines of flight.  Per iteration: the time of a long
+    replayed window (no checks), and, for each roughness constant, the
+    solve under the paper's stopping rule (relative change of f below 1e-9,
+    checked every iteration, at most --pet-max-iters iterations).  The
+    oracle's float64 iteration is timed on a few iterations for the CPU
+    figure."""
+    import torch
+
+    from oracle import pet_oracle
+    from paper_1003_3272_amd import nmf
+    from synth import generators as gen
+    E, y, _ = gen.pet_problem()
+    d, p = E.shape
+    Ed, yd = torch.from_numpy(E).cuda(), torch.from_numpy(y).cuda()
+    out = {"workload": f"synthetic PET: {int(np.sqrt(p))}x{int(np.sqrt(p))} phantom, {d} lines "
+                       "of flight of a 64-detector ring, Poisson counts of mean 50, start "
+                       "lambda = 1, fp32 products, fp64 objective",
+           "d": d, "p": p, "nnz_E": int(np.count_nonzero(E)), "mus": {}}
+    window = 2000
+
+    def per_iter_us(mu, layout):
+        ld = torch.ones(p, dtype=torch.float32, device="cuda")
+        with nmf.Pet(Ed, yd, ld, 64, 64, mu, layout=layout) as m:
+            m.step(32)                       # graphs captured and warm
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            m.step(window)
+            torch.cuda.synchronize()
+            return 1e6 * (time.perf_counter() - t) / window, m.layout
+
+    it_dense, _ = per_iter_us(1e-6, "dense")
+    out["dense_layout_us_per_iter"] = round(it_dense, 2)
+    for mu in args.pet_mus:
+        it_us, out["layout"] = per_iter_us(mu, "auto")
+        ld = torch.ones(p, dtype=torch.float32, device="cuda")
+        with nmf.Pet(Ed, yd, ld, 64, 64, mu) as m:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            conv, iters, f = m.solve(args.pet_max_iters, tol=1e-9, check_every=1)
+            el = time.perf_counter() - t
+        out["mus"][repr(mu)] = {"us_per_iter": round(it_us, 2), "solve_s": round(el, 4),
+                                "iters": iters, "converged": conv, "f": f}
+        log(f"pet mu={mu}: {it_us:.1f} us/iter, solve {iters} iters in {el:.3f} s "
+            f"({'converged' if conv else 'cap'}), f={f:.10g}")
+    # one iteration reads the nonzeros of E_s twice (by lines, by pixels) as
+    # (float32 value, int32 index) pairs, and gathers lambda and the ratios
+    nnz = out["nnz_E"]
+    bytes_iter = 2 * 8.0 * nnz
+    best = min(v["us_per_iter"] for v in out["mus"].values())
+    out["bytes_per_iter"] = bytes_iter
+    out["effective_gbs"] = round(bytes_iter / (best * 1e-6) / 1e9, 1)
+    out["paper_gpu_s_per_iter"] = "282 s / 100000 iterations (GTX 280, Table 3): context only"
+    log(f"pet: {best:.1f} us/iter ({out['layout']}), dense layout {it_dense:.1f} us/iter")
+    Es = pet_oracle.scale_columns(E)
+    pairs = pet_oracle.neighbour_pairs(64, 64)
+    lam = np.ones(p)
+    t = time.perf_counter()
+    k = 0
+    while k < 5 or time.perf_counter() - t < 2.0:
+        lam = pet_oracle.step(Es, y, lam, 1e-6, pairs)
+        k += 1
+    out["oracle_s_per_iter"] = round((time.perf_counter() - t) / k, 5)
+    out["oracle_sample"] = f"{k} float64 iterations of the oracle at mu = 1e-6"
     return out
 
 
@@ -735,6 +807,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_stream_reference:
         out["hbm_reference"] = stream_reference()
+    if not args.no_pet:
+        out["pet"] = pet_experiment(args, log)
+        torch.cuda.empty_cache()
     if not args.no_precision_tier:
         out["precision_tier"] = precision_tier_experiment(args, log)
         torch.cuda.empty_cache()

@@ -439,14 +439,32 @@ nmf_status nmf_batch_solve(const nmf_problem* probs, int32_t count,
    carry; b includes it.  float32 products, float64 objective. */
 typedef struct nmf_pet nmf_pet;
 
+/* How the scaled E is held on the device.  DENSE: E_s and its transpose,
+   read with coalesced row dot products.  SPARSE: the nonzeros of every line
+   and of every pixel in padded rows of (value, index) pairs; a line of
+   flight crosses O(sqrt p) pixels, so a ring scanner's E is about 2%
+   dense.  AUTO takes SPARSE when the longest line and the longest pixel
+   column each hold at most a quarter of a dense row. */
+typedef enum nmf_pet_layout_kind {
+  NMF_PET_AUTO = 0,
+  NMF_PET_DENSE = 1,
+  NMF_PET_SPARSE = 2
+} nmf_pet_layout_kind;
+
 /* E (d x p row-major), y (d) and lambda (p) are device pointers, 16-byte
-   aligned; p = rows * cols, a multiple of 4; mu >= 0.  E and y are copied
-   (E scaled) at creation; lambda is the caller's start (Algorithm 2 uses
-   all ones), updated in place by every step, and must outlive the object.
-   Errors: NMF_EINVAL, NMF_EUNSUPPORTED (p not a multiple of 4), NMF_ENOMEM. */
+   aligned; p = rows * cols, a multiple of 4; mu >= 0; layout one of
+   nmf_pet_layout_kind.  E, y and lambda must be finite and nonnegative
+   (checked on the device).  E and y are copied (E scaled) at creation;
+   lambda is the caller's start (Algorithm 2 uses all ones), updated in
+   place by every step, and must outlive the object.  Synchronizes.
+   Errors: NMF_EINVAL (arguments or data), NMF_EUNSUPPORTED (p not a
+   multiple of 4), NMF_ENOMEM, NMF_EDEVICE. */
 nmf_status nmf_pet_create(nmf_pet** out, const float* E, int64_t d, int64_t p,
                           const float* y, int32_t rows, int32_t cols, double mu,
-                          float* lambda, void* stream);
+                          float* lambda, int32_t layout, void* stream);
+
+/* The layout chosen at creation (NMF_PET_DENSE or NMF_PET_SPARSE). */
+nmf_status nmf_pet_layout(const nmf_pet* m, int32_t* layout);
 
 /* Enqueue `iters` iterations (replayed from HIP graphs of 16, 8, 4, 2 and 1
    iterations).  Asynchronous. */

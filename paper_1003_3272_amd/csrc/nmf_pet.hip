@@ -1,7 +1,7 @@
 // gfx950 kernels and C ABI of the penalized PET reconstruction MM algorithm,
 // Sec. 3.2 (Algorithm 2).  Intensities lambda (p pixels on a rows x cols
-// grid), geometry E (d lines x p pixels, dense), counts y (d).  Every
-// iteration, for all pixels in parallel:
+// grid), geometry E (d lines x p pixels), counts y (d).  Every iteration,
+// for all pixels in parallel:
 //   ratio_i  = y_i / (E_s lambda)_i                  (0 where y_i = 0)
 //   c_j      = lambda_j sum_i e_ij ratio_i           (= sum_i z_ij)
 //   b_j      = mu (|N_j| lambda_j + sum_{k in N_j} lambda_k) - 1
@@ -15,15 +15,23 @@
 // and in the printed form when b > 0, where it does not cancel; at mu = 0
 // the update is c, the EM update (eq. PET_algorithm).
 //
-// Layout: E_s (d x p) and its transpose (p x dpad), row-major, float32, so
-// that both products are row dot products read with coalesced 16-byte loads
-// (one wave per line, then one wave per pixel); partial sums combine in a
+// Two layouts of E_s, chosen at creation.  Dense: E_s (d x p) and its
+// transpose (p x dpad), row-major float32, so that both products are row
+// dot products read with coalesced 16-byte loads (one wave per line, then
+// one wave per pixel).  Sparse (a line of flight crosses O(sqrt p) pixels,
+// so E_s of a ring scanner is about 2% dense): E_s by lines and by pixels in
+// padded rows (ELL) of (value, index) pairs in increasing index order, a
+// wave per line and a group of 16, 32 or 64 lanes per pixel, lambda and the
+// ratios gathered from L2.  An iteration reads src intensities and writes
+// dst (ping-pong between the caller's buffer and a workspace copy, so the
+// neighbour sums never see a half-updated image); partial sums combine in a
 // fixed order, so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <new>
 
 #include "../../include/nmf.h"
@@ -35,9 +43,10 @@ namespace {
 
 inline int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-__device__ __forceinline__ float wave_sum(float s) {
+template <int G>
+__device__ __forceinline__ float group_sum(float s) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   return s;
 }
 __device__ __forceinline__ double wave_sum_d(double s) {
@@ -45,20 +54,78 @@ __device__ __forceinline__ double wave_sum_d(double s) {
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   return s;
 }
+__device__ __forceinline__ int wave_sum_i(int s) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
 
-// Column sums of E (d x p), float64 in a fixed order: one wave per column.
+// ---- set-up ----------------------------------------------------------------
+
+// Column sums of E (float64, fixed order) and nonzeros per column: one wave
+// per column.
 __global__ __launch_bounds__(256) void k_pet_colsum(const float* __restrict__ E, int64_t d,
-                                                    int64_t p, double* __restrict__ colsum) {
+                                                    int64_t p, double* __restrict__ colsum,
+                                                    int32_t* __restrict__ colcnt) {
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j >= p) return;
   double s = 0.0;
-  for (int64_t i = lane; i < d; i += 64) s += (double)E[i * p + j];
+  int cnt = 0;
+  for (int64_t i = lane; i < d; i += 64) {
+    const float v = E[i * p + j];
+    s += (double)v;
+    cnt += v != 0.f;
+  }
   s = wave_sum_d(s);
-  if (lane == 0) colsum[j] = s;
+  cnt = wave_sum_i(cnt);
+  if (lane == 0) {
+    colsum[j] = s;
+    colcnt[j] = cnt;
+  }
 }
 
-// E_s = E / colsum (zero columns stay zero) into Es (d x p) and EsT
+// Nonzeros per line: one wave per line.
+__global__ __launch_bounds__(256) void k_pet_rowcnt(const float* __restrict__ E, int64_t d,
+                                                    int64_t p, int32_t* __restrict__ rowcnt) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= d) return;
+  int cnt = 0;
+  for (int64_t j = lane; j < p; j += 64) cnt += E[i * p + j] != 0.f;
+  cnt = wave_sum_i(cnt);
+  if (lane == 0) rowcnt[i] = cnt;
+}
+
+// out[0] = largest line count, out[1] = largest pixel count (one block).
+__global__ void k_pet_maxcnt(const int32_t* __restrict__ rowcnt, int64_t d,
+                             const int32_t* __restrict__ colcnt, int64_t p,
+                             double* __restrict__ out) {
+  __shared__ int sm[2][256];
+  int a = 0, b = 0;
+  for (int64_t i = threadIdx.x; i < d; i += 256) a = max(a, rowcnt[i]);
+  for (int64_t j = threadIdx.x; j < p; j += 256) b = max(b, colcnt[j]);
+  sm[0][threadIdx.x] = a;
+  sm[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[0][threadIdx.x] = max(sm[0][threadIdx.x], sm[0][threadIdx.x + s]);
+      sm[1][threadIdx.x] = max(sm[1][threadIdx.x], sm[1][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = (double)sm[0][0];
+    out[1] = (double)sm[1][0];
+  }
+}
+
+__device__ __forceinline__ float scaled(float e, double cs) {
+  return cs > 0.0 ? (float)((double)e / cs) : 0.f;
+}
+
+// Dense: E_s = E / colsum (zero columns stay zero) into Es (d x p) and EsT
 // (p x dpad, padding zero).
 __global__ void k_pet_scale(const float* __restrict__ E, int64_t d, int64_t p,
                             const double* __restrict__ colsum, float* __restrict__ Es,
@@ -67,14 +134,89 @@ __global__ void k_pet_scale(const float* __restrict__ E, int64_t d, int64_t p,
   for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * 256) {
     const int64_t i = idx / p, j = idx % p;
-    const double cs = colsum[j];
-    const float v = cs > 0.0 ? (float)((double)E[idx] / cs) : 0.f;
+    const float v = scaled(E[idx], colsum[j]);
     Es[idx] = v;
     EsT[j * dpad + i] = v;
   }
 }
 
-// ratio_i = y_i / (E_s lambda)_i (0 where y_i = 0): one wave per line.
+// Sparse, by lines: the nonzeros of line i in increasing pixel order, packed
+// by a wave-wide ballot.  One wave per line.
+__global__ __launch_bounds__(256) void k_pet_fill_rows(const float* __restrict__ E, int64_t d,
+                                                       int64_t p, const double* __restrict__ colsum,
+                                                       int64_t wr, float* __restrict__ val,
+                                                       int32_t* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= d) return;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int64_t base = 0;
+  for (int64_t j0 = 0; j0 < p; j0 += 64) {
+    const int64_t j = j0 + lane;
+    const float v = j < p ? E[i * p + j] : 0.f;
+    const uint64_t mask = __ballot(v != 0.f);
+    if (v != 0.f) {
+      const int64_t at = i * wr + base + __popcll(mask & below);
+      val[at] = scaled(v, colsum[j]);
+      idx[at] = (int32_t)j;
+    }
+    base += __popcll(mask);
+  }
+}
+
+// Sparse, by pixels: the nonzeros of column j in increasing line order.  One
+// wave per pixel (column reads are strided; this runs once).
+__global__ __launch_bounds__(256) void k_pet_fill_cols(const float* __restrict__ E, int64_t d,
+                                                       int64_t p, const double* __restrict__ colsum,
+                                                       int64_t wc, float* __restrict__ val,
+                                                       int32_t* __restrict__ idx) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= p) return;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const double cs = colsum[j];
+  int64_t base = 0;
+  for (int64_t i0 = 0; i0 < d; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const float v = i < d ? E[i * p + j] : 0.f;
+    const uint64_t mask = __ballot(v != 0.f);
+    if (v != 0.f) {
+      const int64_t at = j * wc + base + __popcll(mask & below);
+      val[at] = scaled(v, cs);
+      idx[at] = (int32_t)i;
+    }
+    base += __popcll(mask);
+  }
+}
+
+// ---- one iteration ---------------------------------------------------------
+
+__device__ __forceinline__ float ratio_of(float y, float s) { return y > 0.f ? y / s : 0.f; }
+
+// The positive root for pixel j from t = (E_s^T ratio)_j and the source
+// image.
+__device__ __forceinline__ float pet_root(float t, const float* __restrict__ lam, int64_t j,
+                                          int rows, int cols, float mu) {
+  const float lj = lam[j];
+  const float c = lj * t;
+  const int r = (int)(j / cols), cc = (int)(j % cols);
+  float cnt = 0.f, nsum = 0.f;
+  if (r > 0) { cnt += 1.f; nsum += lam[j - cols]; }
+  if (r + 1 < rows) { cnt += 1.f; nsum += lam[j + cols]; }
+  if (cc > 0) { cnt += 1.f; nsum += lam[j - 1]; }
+  if (cc + 1 < cols) { cnt += 1.f; nsum += lam[j + 1]; }
+  const float b = mu * (cnt * lj + nsum) - 1.f;
+  const float a = -2.f * mu * cnt;
+  if (a == 0.f) return c;
+  // a < 0 and c >= 0: the roots have opposite signs (or one is 0), and the
+  // positive one is (b + s) / (-2a) = 2c / (s - b), s = sqrt(b^2 - 4ac);
+  // take the form whose sum does not cancel
+  const float s = sqrtf(fmaxf(b * b - 4.f * a * c, 0.f));
+  if (b > 0.f) return (b + s) / (-2.f * a);
+  return s - b > 0.f ? 2.f * c / (s - b) : 0.f;
+}
+
+// Dense ratio_i: one wave per line.
 __global__ __launch_bounds__(256) void k_pet_forward(const float* __restrict__ Es, int64_t d,
                                                      int64_t p, const float* __restrict__ lam,
                                                      const float* __restrict__ y,
@@ -92,11 +234,11 @@ __global__ __launch_bounds__(256) void k_pet_forward(const float* __restrict__ E
     s = fmaf(e.z, l.z, s);
     s = fmaf(e.w, l.w, s);
   }
-  s = wave_sum(s);
-  if (lane == 0) ratio[i] = y[i] > 0.f ? y[i] / s : 0.f;
+  s = group_sum<64>(s);
+  if (lane == 0) ratio[i] = ratio_of(y[i], s);
 }
 
-// c_j = lambda_j (E_s^T ratio)_j and the positive root: one wave per pixel.
+// Dense update: one wave per pixel.
 __global__ __launch_bounds__(256) void k_pet_backward(const float* __restrict__ EsT, int64_t dpad,
                                                       int64_t p, const float* __restrict__ ratio,
                                                       const float* __restrict__ lam, int rows,
@@ -115,30 +257,50 @@ __global__ __launch_bounds__(256) void k_pet_backward(const float* __restrict__ 
     t = fmaf(e.z, q.z, t);
     t = fmaf(e.w, q.w, t);
   }
-  t = wave_sum(t);
-  if (lane != 0) return;
-  const float lj = lam[j];
-  const float c = lj * t;
-  const int r = (int)(j / cols), cc = (int)(j % cols);
-  float cnt = 0.f, nsum = 0.f;
-  if (r > 0) { cnt += 1.f; nsum += lam[j - cols]; }
-  if (r + 1 < rows) { cnt += 1.f; nsum += lam[j + cols]; }
-  if (cc > 0) { cnt += 1.f; nsum += lam[j - 1]; }
-  if (cc + 1 < cols) { cnt += 1.f; nsum += lam[j + 1]; }
-  const float b = mu * (cnt * lj + nsum) - 1.f;
-  const float a = -2.f * mu * cnt;
-  float v = c;
-  if (a != 0.f) {
-    // a < 0 and c >= 0: the roots have opposite signs (or one is 0), and
-    // the positive one is (b + s) / (-2a) = 2c / (s - b), s = sqrt(b^2 - 4ac);
-    // take the form whose sum does not cancel
-    const float s = sqrtf(fmaxf(b * b - 4.f * a * c, 0.f));
-    if (b > 0.f)
-      v = (b + s) / (-2.f * a);
-    else
-      v = s - b > 0.f ? 2.f * c / (s - b) : 0.f;
-  }
-  out[j] = v;
+  t = group_sum<64>(t);
+  if (lane == 0) out[j] = pet_root(t, lam, j, rows, cols, mu);
+}
+
+// Sparse ratio_i: one wave per line, lane k takes the entries k, k + 64, ...
+__global__ __launch_bounds__(256) void k_pet_forward_ell(const float* __restrict__ val,
+                                                         const int32_t* __restrict__ idx,
+                                                         const int32_t* __restrict__ cnt,
+                                                         int64_t wr, int64_t d,
+                                                         const float* __restrict__ lam,
+                                                         const float* __restrict__ y,
+                                                         float* __restrict__ ratio) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= d) return;
+  const int n = cnt[i];
+  const float* v = val + i * wr;
+  const int32_t* ix = idx + i * wr;
+  float s = 0.f;
+  for (int k = lane; k < n; k += 64) s = fmaf(v[k], lam[ix[k]], s);
+  s = group_sum<64>(s);
+  if (lane == 0) ratio[i] = ratio_of(y[i], s);
+}
+
+// Sparse update: a group of G lanes per pixel (G divides 64).
+template <int G>
+__global__ __launch_bounds__(256) void k_pet_backward_ell(const float* __restrict__ val,
+                                                          const int32_t* __restrict__ idx,
+                                                          const int32_t* __restrict__ cnt,
+                                                          int64_t wc, int64_t p,
+                                                          const float* __restrict__ ratio,
+                                                          const float* __restrict__ lam, int rows,
+                                                          int cols, float mu,
+                                                          float* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int g = threadIdx.x % G;
+  if (j >= p) return;  // whole groups leave together
+  const int n = cnt[j];
+  const float* v = val + j * wc;
+  const int32_t* ix = idx + j * wc;
+  float t = 0.f;
+  for (int k = g; k < n; k += G) t = fmaf(v[k], ratio[ix[k]], t);
+  t = group_sum<G>(t);
+  if (g == 0) out[j] = pet_root(t, lam, j, rows, cols, mu);
 }
 
 __global__ void k_pet_copy(const float* __restrict__ src, float* __restrict__ dst, int64_t p) {
@@ -146,9 +308,26 @@ __global__ void k_pet_copy(const float* __restrict__ src, float* __restrict__ ds
     dst[j] = src[j];
 }
 
-// Objective partials (float64): part[i] = y_i ln B_i - B_i for the lines,
-// B_i from float64 products; part[d + j] = -(mu / 2) [(lambda_j -
-// lambda_right)^2 + (lambda_j - lambda_below)^2] for the pixels.
+// ---- objective (float64) -----------------------------------------------------
+
+// -(mu / 2) [(lambda_j - lambda_right)^2 + (lambda_j - lambda_below)^2]:
+// every neighbour pair once.
+__device__ __forceinline__ double pet_penalty_part(const float* __restrict__ lam, int64_t j,
+                                                   int rows, int cols, double mu) {
+  const int r = (int)(j / cols), cc = (int)(j % cols);
+  const double lj = lam[j];
+  double pen = 0.0;
+  if (cc + 1 < cols) pen += (lj - lam[j + 1]) * (lj - lam[j + 1]);
+  if (r + 1 < rows) pen += (lj - lam[j + cols]) * (lj - lam[j + cols]);
+  return -0.5 * mu * pen;
+}
+
+__device__ __forceinline__ double line_term(float y, double b) {
+  return (y > 0.f ? (double)y * log(b) : 0.0) - b;
+}
+
+// part[i] = y_i ln B_i - B_i (B_i in float64) for the lines, then the
+// penalty parts; one wave per line, then one wave per 64 pixels.
 __global__ __launch_bounds__(256) void k_pet_objective(const float* __restrict__ Es, int64_t d,
                                                        int64_t p, const float* __restrict__ lam,
                                                        const float* __restrict__ y, int rows,
@@ -161,17 +340,30 @@ __global__ __launch_bounds__(256) void k_pet_objective(const float* __restrict__
     double s = 0.0;
     for (int64_t j = lane; j < p; j += 64) s = fma((double)row[j], (double)lam[j], s);
     s = wave_sum_d(s);
-    if (lane == 0) part[w] = (y[w] > 0.f ? (double)y[w] * log(s) : 0.0) - s;
+    if (lane == 0) part[w] = line_term(y[w], s);
   } else if (w < d + (p + 63) / 64) {
     const int64_t j = (w - d) * 64 + lane;
-    if (j < p) {
-      const int r = (int)(j / cols), cc = (int)(j % cols);
-      const double lj = lam[j];
-      double pen = 0.0;
-      if (cc + 1 < cols) pen += (lj - lam[j + 1]) * (lj - lam[j + 1]);
-      if (r + 1 < rows) pen += (lj - lam[j + cols]) * (lj - lam[j + cols]);
-      part[d + j] = -0.5 * mu * pen;
-    }
+    if (j < p) part[d + j] = pet_penalty_part(lam, j, rows, cols, mu);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pet_objective_ell(
+    const float* __restrict__ val, const int32_t* __restrict__ idx, const int32_t* __restrict__ cnt,
+    int64_t wr, int64_t d, int64_t p, const float* __restrict__ lam, const float* __restrict__ y,
+    int rows, int cols, double mu, double* __restrict__ part) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w < d) {
+    const int n = cnt[w];
+    const float* v = val + w * wr;
+    const int32_t* ix = idx + w * wr;
+    double s = 0.0;
+    for (int k = lane; k < n; k += 64) s = fma((double)v[k], (double)lam[ix[k]], s);
+    s = wave_sum_d(s);
+    if (lane == 0) part[w] = line_term(y[w], s);
+  } else if (w < d + (p + 63) / 64) {
+    const int64_t j = (w - d) * 64 + lane;
+    if (j < p) part[d + j] = pet_penalty_part(lam, j, rows, cols, mu);
   }
 }
 
@@ -190,10 +382,19 @@ struct nmf_pet {
   int rows = 0, cols = 0;
   float mu = 0.f;
   double mu_d = 0.0;
-  float* lam = nullptr;  // caller's intensities, updated in place
-  void* ws = nullptr;
-  float *Es = nullptr, *EsT = nullptr, *y = nullptr, *ratio = nullptr, *tmp = nullptr;
+  bool sparse = false;
+  int64_t wr = 0, wc = 0;  // ELL widths (sparse)
+  int group = 64;          // lanes per pixel in the sparse update
+  float* lam = nullptr;    // caller's intensities, updated in place
+  void* ws = nullptr;      // fixed-size part
+  void* ws_e = nullptr;    // the layout of E_s
+  float *y = nullptr, *ratio = nullptr, *lam2 = nullptr;
   double *colsum = nullptr, *part = nullptr;
+  int32_t *rowcnt = nullptr, *colcnt = nullptr;
+  uint32_t* flag = nullptr;
+  float *Es = nullptr, *EsT = nullptr;       // dense
+  float *rval = nullptr, *cval = nullptr;    // sparse values
+  int32_t *ridx = nullptr, *cidx = nullptr;  // sparse indices
   double* hostbuf = nullptr;      // pinned, coherent
   double* hostbuf_dev = nullptr;  // the same memory as the device addresses it
   hipStream_t cap_stream = nullptr;
@@ -207,16 +408,51 @@ namespace {
     if ((expr) != hipSuccess) return NMF_EDEVICE;   \
   } while (0)
 
-nmf_status pet_iter(nmf_pet* m) {
-  hipLaunchKernelGGL(k_pet_forward, dim3((unsigned)((m->d + 3) / 4)), dim3(256), 0, m->st, m->Es,
-                     m->d, m->p, m->lam, m->y, m->ratio);
+nmf_status pet_iter(nmf_pet* m, const float* src, float* dst) {
+  const unsigned lines = (unsigned)((m->d + 3) / 4);
+  if (!m->sparse) {
+    hipLaunchKernelGGL(k_pet_forward, dim3(lines), dim3(256), 0, m->st, m->Es, m->d, m->p, src,
+                       m->y, m->ratio);
+    PTRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_pet_backward, dim3((unsigned)((m->p + 3) / 4)), dim3(256), 0, m->st,
+                       m->EsT, m->dpad, m->p, m->ratio, src, m->rows, m->cols, m->mu, dst);
+    PTRY_HIP(hipGetLastError());
+    return NMF_OK;
+  }
+  hipLaunchKernelGGL(k_pet_forward_ell, dim3(lines), dim3(256), 0, m->st, m->rval, m->ridx,
+                     m->rowcnt, m->wr, m->d, src, m->y, m->ratio);
   PTRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_pet_backward, dim3((unsigned)((m->p + 3) / 4)), dim3(256), 0, m->st,
-                     m->EsT, m->dpad, m->p, m->ratio, m->lam, m->rows, m->cols, m->mu, m->tmp);
+  const int g = m->group;
+  const unsigned blocks = (unsigned)((m->p + 256 / g - 1) / (256 / g));
+  if (g == 16)
+    hipLaunchKernelGGL(k_pet_backward_ell<16>, dim3(blocks), dim3(256), 0, m->st, m->cval,
+                       m->cidx, m->colcnt, m->wc, m->p, m->ratio, src, m->rows, m->cols, m->mu,
+                       dst);
+  else if (g == 32)
+    hipLaunchKernelGGL(k_pet_backward_ell<32>, dim3(blocks), dim3(256), 0, m->st, m->cval,
+                       m->cidx, m->colcnt, m->wc, m->p, m->ratio, src, m->rows, m->cols, m->mu,
+                       dst);
+  else
+    hipLaunchKernelGGL(k_pet_backward_ell<64>, dim3(blocks), dim3(256), 0, m->st, m->cval,
+                       m->cidx, m->colcnt, m->wc, m->p, m->ratio, src, m->rows, m->cols, m->mu,
+                       dst);
   PTRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_pet_copy, dim3(pblocks(m->p, 1024)), dim3(256), 0, m->st, m->tmp, m->lam,
-                     m->p);
-  PTRY_HIP(hipGetLastError());
+  return NMF_OK;
+}
+
+// `iters` iterations from and back into the caller's buffer: they alternate
+// caller -> copy -> caller, and an odd count ends with a copy back.
+nmf_status pet_iters(nmf_pet* m, int iters) {
+  for (int it = 0; it < iters; ++it) {
+    const bool even = (it & 1) == 0;
+    nmf_status s = pet_iter(m, even ? m->lam : m->lam2, even ? m->lam2 : m->lam);
+    if (s != NMF_OK) return s;
+  }
+  if (iters & 1) {
+    hipLaunchKernelGGL(k_pet_copy, dim3(pblocks(m->p, 1024)), dim3(256), 0, m->st, m->lam2,
+                       m->lam, m->p);
+    PTRY_HIP(hipGetLastError());
+  }
   return NMF_OK;
 }
 
@@ -229,7 +465,7 @@ nmf_status pet_capture(nmf_pet* m, int iters, hipGraphExec_t* out) {
   if (hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     s = NMF_EDEVICE;
   if (s == NMF_OK) {
-    for (int it = 0; it < iters && s == NMF_OK; ++it) s = pet_iter(m);
+    s = pet_iters(m, iters);
     const hipError_t e = hipStreamEndCapture(m->cap_stream, &graph);
     if (s == NMF_OK && (e != hipSuccess || !graph)) s = NMF_EDEVICE;
   }
@@ -243,8 +479,14 @@ nmf_status pet_capture(nmf_pet* m, int iters, hipGraphExec_t* out) {
 
 nmf_status pet_objective_sync(nmf_pet* m, double* f) {
   const int64_t waves = m->d + (m->p + 63) / 64;
-  hipLaunchKernelGGL(k_pet_objective, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, m->st,
-                     m->Es, m->d, m->p, m->lam, m->y, m->rows, m->cols, m->mu_d, m->part);
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  if (m->sparse)
+    hipLaunchKernelGGL(k_pet_objective_ell, dim3(blocks), dim3(256), 0, m->st, m->rval, m->ridx,
+                       m->rowcnt, m->wr, m->d, m->p, m->lam, m->y, m->rows, m->cols, m->mu_d,
+                       m->part);
+  else
+    hipLaunchKernelGGL(k_pet_objective, dim3(blocks), dim3(256), 0, m->st, m->Es, m->d, m->p,
+                       m->lam, m->y, m->rows, m->cols, m->mu_d, m->part);
   PTRY_HIP(hipGetLastError());
   PTRY_HIP(launch_reduce_f64(m->part, m->d + m->p, m->hostbuf_dev, m->st));
   PTRY_HIP(hipStreamSynchronize(m->st));
@@ -257,9 +499,106 @@ void pet_free(nmf_pet* m) {
   for (hipGraphExec_t g : m->gp)
     if (g) (void)hipGraphExecDestroy(g);
   if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+  if (m->ws_e) (void)hipFree(m->ws_e);
   if (m->ws) (void)hipFree(m->ws);
   if (m->hostbuf) (void)hipHostFree(m->hostbuf);
   delete m;
+}
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+
+// Workspace, validation, counts and the layout of E_s.  Synchronizes.
+nmf_status pet_setup(nmf_pet* m, const float* E, const float* y, int32_t layout) {
+  const int64_t d = m->d, p = m->p;
+  Carver a;
+  const size_t oy = a.take(4 * (size_t)m->dpad), orat = a.take(4 * (size_t)m->dpad);
+  const size_t olam2 = a.take(4 * (size_t)p), ocs = a.take(8 * (size_t)p);
+  const size_t opart = a.take(8 * (size_t)(d + p)), orc = a.take(4 * (size_t)d);
+  const size_t occ = a.take(4 * (size_t)p), ofl = a.take(4);
+  if (hipMalloc(&m->ws, a.off) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&m->hostbuf), 4 * sizeof(double),
+                    hipHostMallocCoherent) != hipSuccess) {
+    (void)hipGetLastError();
+    return NMF_ENOMEM;
+  }
+  PTRY_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&m->hostbuf_dev), m->hostbuf, 0));
+  char* b = static_cast<char*>(m->ws);
+  m->y = reinterpret_cast<float*>(b + oy);
+  m->ratio = reinterpret_cast<float*>(b + orat);
+  m->lam2 = reinterpret_cast<float*>(b + olam2);
+  m->colsum = reinterpret_cast<double*>(b + ocs);
+  m->part = reinterpret_cast<double*>(b + opart);
+  m->rowcnt = reinterpret_cast<int32_t*>(b + orc);
+  m->colcnt = reinterpret_cast<int32_t*>(b + occ);
+  m->flag = reinterpret_cast<uint32_t*>(b + ofl);
+  // zero everything (the ratios' padding must read as zero)
+  PTRY_HIP(launch_fill_u32(static_cast<uint32_t*>(m->ws), (int64_t)(a.off / 4), 0u, m->st));
+  // E, y and the start must be finite and nonnegative
+  PTRY_HIP(launch_validate(E, p, d, p, m->flag, m->st));
+  PTRY_HIP(launch_validate(y, d, 1, d, m->flag, m->st));
+  PTRY_HIP(launch_validate(m->lam, p, 1, p, m->flag, m->st));
+  hipLaunchKernelGGL(k_pet_colsum, dim3((unsigned)((p + 3) / 4)), dim3(256), 0, m->st, E, d, p,
+                     m->colsum, m->colcnt);
+  hipLaunchKernelGGL(k_pet_rowcnt, dim3((unsigned)((d + 3) / 4)), dim3(256), 0, m->st, E, d, p,
+                     m->rowcnt);
+  hipLaunchKernelGGL(k_pet_maxcnt, dim3(1), dim3(256), 0, m->st, m->rowcnt, d, m->colcnt, p,
+                     m->hostbuf_dev);
+  PTRY_HIP(hipGetLastError());
+  PTRY_HIP(hipMemcpyAsync(m->y, y, 4 * (size_t)d, hipMemcpyDeviceToDevice, m->st));
+  PTRY_HIP(hipMemcpyAsync(m->hostbuf + 2, m->flag, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          m->st));
+  PTRY_HIP(hipStreamSynchronize(m->st));
+  uint32_t bad;
+  std::memcpy(&bad, m->hostbuf + 2, sizeof(bad));
+  if (bad) return NMF_EINVAL;
+  const int64_t maxrow = (int64_t)m->hostbuf[0], maxcol = (int64_t)m->hostbuf[1];
+  // the padded rows pay when each is at most a quarter of a dense one
+  m->sparse = layout == NMF_PET_SPARSE ||
+              (layout == NMF_PET_AUTO && 4 * maxrow <= p && 4 * maxcol <= d);
+  Carver e;
+  if (!m->sparse) {
+    const size_t oEs = e.take(4 * (size_t)d * p), oEsT = e.take(4 * (size_t)p * m->dpad);
+    if (hipMalloc(&m->ws_e, e.off) != hipSuccess) {
+      (void)hipGetLastError();
+      return NMF_ENOMEM;
+    }
+    char* q = static_cast<char*>(m->ws_e);
+    m->Es = reinterpret_cast<float*>(q + oEs);
+    m->EsT = reinterpret_cast<float*>(q + oEsT);
+    PTRY_HIP(launch_fill_u32(static_cast<uint32_t*>(m->ws_e), (int64_t)(e.off / 4), 0u, m->st));
+    hipLaunchKernelGGL(k_pet_scale, dim3(pblocks(d * p)), dim3(256), 0, m->st, E, d, p, m->colsum,
+                       m->Es, m->EsT, m->dpad);
+  } else {
+    m->wr = std::max<int64_t>(rup(maxrow, 4), 4);
+    m->wc = std::max<int64_t>(rup(maxcol, 4), 4);
+    m->group = maxcol > 32 ? 64 : (maxcol > 16 ? 32 : 16);
+    const size_t orv = e.take(4 * (size_t)d * m->wr), ori = e.take(4 * (size_t)d * m->wr);
+    const size_t ocv = e.take(4 * (size_t)p * m->wc), oci = e.take(4 * (size_t)p * m->wc);
+    if (hipMalloc(&m->ws_e, e.off) != hipSuccess) {
+      (void)hipGetLastError();
+      return NMF_ENOMEM;
+    }
+    char* q = static_cast<char*>(m->ws_e);
+    m->rval = reinterpret_cast<float*>(q + orv);
+    m->ridx = reinterpret_cast<int32_t*>(q + ori);
+    m->cval = reinterpret_cast<float*>(q + ocv);
+    m->cidx = reinterpret_cast<int32_t*>(q + oci);
+    PTRY_HIP(launch_fill_u32(static_cast<uint32_t*>(m->ws_e), (int64_t)(e.off / 4), 0u, m->st));
+    hipLaunchKernelGGL(k_pet_fill_rows, dim3((unsigned)((d + 3) / 4)), dim3(256), 0, m->st, E, d,
+                       p, m->colsum, m->wr, m->rval, m->ridx);
+    hipLaunchKernelGGL(k_pet_fill_cols, dim3((unsigned)((p + 3) / 4)), dim3(256), 0, m->st, E, d,
+                       p, m->colsum, m->wc, m->cval, m->cidx);
+  }
+  PTRY_HIP(hipGetLastError());
+  PTRY_HIP(hipStreamSynchronize(m->st));
+  return NMF_OK;
 }
 
 }  // namespace
@@ -267,11 +606,13 @@ void pet_free(nmf_pet* m) {
 extern "C" {
 
 nmf_status nmf_pet_create(nmf_pet** out, const float* E, int64_t d, int64_t p, const float* y,
-                          int32_t rows, int32_t cols, double mu, float* lambda, void* stream) {
+                          int32_t rows, int32_t cols, double mu, float* lambda, int32_t layout,
+                          void* stream) {
   if (!out) return NMF_EINVAL;
   *out = nullptr;
   if (!E || !y || !lambda || d < 1 || p < 1 || rows < 1 || cols < 1) return NMF_EINVAL;
   if ((int64_t)rows * cols != p || !(mu >= 0.0) || !std::isfinite(mu)) return NMF_EINVAL;
+  if (layout < NMF_PET_AUTO || layout > NMF_PET_SPARSE) return NMF_EINVAL;
   for (const void* q : {static_cast<const void*>(E), static_cast<const void*>(y),
                         static_cast<const void*>(lambda)})
     if (reinterpret_cast<uintptr_t>(q) % 16 != 0) return NMF_EINVAL;
@@ -287,55 +628,19 @@ nmf_status nmf_pet_create(nmf_pet** out, const float* E, int64_t d, int64_t p, c
   m->mu = (float)mu;
   m->mu_d = mu;
   m->lam = lambda;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off += (bytes + 255) / 256 * 256;
-    return o;
-  };
-  const size_t oEs = take(4 * (size_t)d * p), oEsT = take(4 * (size_t)p * m->dpad);
-  const size_t oy = take(4 * (size_t)m->dpad), orat = take(4 * (size_t)m->dpad);
-  const size_t otmp = take(4 * (size_t)p), ocs = take(8 * (size_t)p);
-  const size_t opart = take(8 * (size_t)(d + p));
-  if (hipMalloc(&m->ws, off) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&m->hostbuf), 4 * sizeof(double),
-                    hipHostMallocCoherent) != hipSuccess) {
-    (void)hipGetLastError();
-    pet_free(m);
-    return NMF_ENOMEM;
-  }
-  nmf_status s = NMF_OK;
-  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&m->hostbuf_dev), m->hostbuf, 0) !=
-      hipSuccess)
-    s = NMF_EDEVICE;
-  char* b = static_cast<char*>(m->ws);
-  m->Es = reinterpret_cast<float*>(b + oEs);
-  m->EsT = reinterpret_cast<float*>(b + oEsT);
-  m->y = reinterpret_cast<float*>(b + oy);
-  m->ratio = reinterpret_cast<float*>(b + orat);
-  m->tmp = reinterpret_cast<float*>(b + otmp);
-  m->colsum = reinterpret_cast<double*>(b + ocs);
-  m->part = reinterpret_cast<double*>(b + opart);
-  // zero everything (the transposed copy's padding and the counts' tail
-  // must read as zero), then scale E and copy y
-  if (s == NMF_OK &&
-      launch_fill_u32(static_cast<uint32_t*>(m->ws), (int64_t)(off / 4), 0u, m->st) != hipSuccess)
-    s = NMF_EDEVICE;
-  if (s == NMF_OK) {
-    hipLaunchKernelGGL(k_pet_colsum, dim3((unsigned)((p + 3) / 4)), dim3(256), 0, m->st, E, d, p,
-                       m->colsum);
-    hipLaunchKernelGGL(k_pet_scale, dim3(pblocks(d * p)), dim3(256), 0, m->st, E, d, p, m->colsum,
-                       m->Es, m->EsT, m->dpad);
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(m->y, y, 4 * (size_t)d, hipMemcpyDeviceToDevice, m->st) != hipSuccess ||
-        hipStreamSynchronize(m->st) != hipSuccess)
-      s = NMF_EDEVICE;
-  }
+  const nmf_status s = pet_setup(m, E, y, layout);
   if (s != NMF_OK) {
+    (void)hipStreamSynchronize(m->st);
     pet_free(m);
     return s;
   }
   *out = m;
+  return NMF_OK;
+}
+
+nmf_status nmf_pet_layout(const nmf_pet* m, int32_t* layout) {
+  if (!m || !layout) return NMF_EINVAL;
+  *layout = m->sparse ? NMF_PET_SPARSE : NMF_PET_DENSE;
   return NMF_OK;
 }
 

@@ -153,8 +153,10 @@ def load(path: str = LIB_PATH):
                                      POINTER(c_int32), POINTER(c_double), P]
     lib.nmf_batch_solve.restype = c_int32
     lib.nmf_pet_create.argtypes = [POINTER(P), P, c_int64, c_int64, P, c_int32, c_int32, c_double,
-                                   P, P]
+                                   P, c_int32, P]
     lib.nmf_pet_create.restype = c_int32
+    lib.nmf_pet_layout.argtypes = [P, POINTER(c_int32)]
+    lib.nmf_pet_layout.restype = c_int32
     lib.nmf_pet_step.argtypes = [P, c_int32]
     lib.nmf_pet_step.restype = c_int32
     lib.nmf_pet_objective.argtypes = [P, POINTER(c_double)]
@@ -604,7 +606,9 @@ class Pet:
     y (d,) float32 CUDA tensors, lam (p,) float32 CUDA tensor updated in
     place, p = rows * cols pixels in row-major order."""
 
-    def __init__(self, E, y, lam, rows, cols, mu, stream=None):
+    LAYOUTS = {"auto": 0, "dense": 1, "sparse": 2}
+
+    def __init__(self, E, y, lam, rows, cols, mu, layout="auto", stream=None):
         import torch
         for name, t in (("E", E), ("y", y), ("lam", lam)):
             if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
@@ -616,7 +620,8 @@ class Pet:
         self._keep = (E, y, lam)
         self._m = c_void_p()
         st = load().nmf_pet_create(byref(self._m), _ptr(E), d, p, _ptr(y), int(rows), int(cols),
-                                   float(mu), _ptr(lam), _stream_handle(stream))
+                                   float(mu), _ptr(lam), self.LAYOUTS[layout],
+                                   _stream_handle(stream))
         if st != NMF_OK:
             self._m = c_void_p()
             raise NmfError(st, "nmf_pet_create")
@@ -625,6 +630,12 @@ class Pet:
         if st not in (NMF_OK, NMF_ENOTCONVERGED):
             raise NmfError(st, what)
         return st
+
+    @property
+    def layout(self):
+        v = c_int32()
+        self._check(load().nmf_pet_layout(self._m, byref(v)), "nmf_pet_layout")
+        return {1: "dense", 2: "sparse"}[v.value]
 
     def step(self, iters=1):
         self._check(load().nmf_pet_step(self._m, int(iters)), "nmf_pet_step")

@@ -220,9 +220,11 @@ def test_pet_calls_reject_bad_arguments_before_device_work():
              (ok[:7] + (FAKE + 4,), nmf.NMF_EINVAL),
              ((FAKE, 10, 10, FAKE, 2, 5, 0.1, FAKE), nmf.NMF_EUNSUPPORTED)]
     for args, code in cases:
-        assert lib.nmf_pet_create(P, *args, None) == code, args
+        assert lib.nmf_pet_create(P, *args, 0, None) == code, args
         assert not out.value
-    assert lib.nmf_pet_create(None, *ok, None) == nmf.NMF_EINVAL
+    assert lib.nmf_pet_create(None, *ok, 0, None) == nmf.NMF_EINVAL
+    assert lib.nmf_pet_create(P, *ok, 3, None) == nmf.NMF_EINVAL      # unknown layout
+    assert lib.nmf_pet_layout(None, ctypes.byref(ctypes.c_int32())) == nmf.NMF_EINVAL
     f, it = ctypes.c_double(), ctypes.c_int32()
     assert lib.nmf_pet_step(None, 1) == nmf.NMF_EINVAL
     assert lib.nmf_pet_objective(None, ctypes.byref(f)) == nmf.NMF_EINVAL

@@ -45,13 +45,15 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _gpu_run(E, y, rows, cols, mu, iters, lam0=None, each=True):
+def _gpu_run(E, y, rows, cols, mu, iters, lam0=None, each=True, layout="auto", expect=None):
     from paper_1003_3272_amd import nmf
     p = E.shape[1]
     lam0 = np.ones(p, np.float32) if lam0 is None else lam0
     Ed, yd, ld = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (E, y, lam0))
     trace = []
-    with nmf.Pet(Ed, yd, ld, rows, cols, mu) as m:
+    with nmf.Pet(Ed, yd, ld, rows, cols, mu, layout=layout) as m:
+        if expect is not None:
+            assert m.layout == expect
         trace.append(m.objective())
         if each:
             for _ in range(iters):
@@ -63,11 +65,13 @@ def _gpu_run(E, y, rows, cols, mu, iters, lam0=None, each=True):
     return ld.cpu().numpy(), np.array(trace)
 
 
+# the ring geometry is about 2% dense: AUTO takes the sparse layout
+@pytest.mark.parametrize("layout,expect", [("auto", "sparse"), ("dense", "dense")])
 @pytest.mark.parametrize("mu", [0.0, 1e-5, 1e-3, 1e-1])
-def test_pet_matches_oracle_full_size(gpu_lib, full_problem, mu):
+def test_pet_matches_oracle_full_size(gpu_lib, full_problem, mu, layout, expect):
     E, y, rows, cols = full_problem
     pairs = O.neighbour_pairs(rows, cols)
-    lam, tr = _gpu_run(E, y, rows, cols, mu, 20)
+    lam, tr = _gpu_run(E, y, rows, cols, mu, 20, layout=layout, expect=expect)
     lam_o, tr_o = O.run(E, y, np.ones(E.shape[1]), mu, pairs, 20)
     err = np.abs(tr - tr_o) / np.abs(tr_o)
     assert err.max() < 1e-5, (mu, err.max(), int(err.argmax()))
@@ -75,11 +79,13 @@ def test_pet_matches_oracle_full_size(gpu_lib, full_problem, mu):
     assert (lam >= 0).all()
 
 
+# 20% dense: AUTO keeps the dense layout
+@pytest.mark.parametrize("layout,expect", [("auto", "dense"), ("sparse", "sparse")])
 @pytest.mark.parametrize("mu", [0.0, 1e-2, 1.0])
-def test_pet_matches_oracle_ragged(gpu_lib, mu):
+def test_pet_matches_oracle_ragged(gpu_lib, mu, layout, expect):
     E, y, rows, cols = _ragged_problem()
     pairs = O.neighbour_pairs(rows, cols)
-    lam, tr = _gpu_run(E, y, rows, cols, mu, 20)
+    lam, tr = _gpu_run(E, y, rows, cols, mu, 20, layout=layout, expect=expect)
     lam_o, tr_o = O.run(E, y, np.ones(E.shape[1]), mu, pairs, 20)
     err = np.abs(tr - tr_o) / np.maximum(np.abs(tr_o), 1.0)
     assert err.max() < 1e-5, (mu, err.max())
@@ -91,6 +97,22 @@ def test_pet_matches_oracle_ragged(gpu_lib, mu):
         assert lam_o[50] > 0
     if mu == 0.0:
         assert lam[50] == 0.0
+
+
+def test_pet_matches_oracle_many_lines_per_pixel(gpu_lib):
+    """301 lines over an 8 x 8 grid, 25% dense: more than 32 lines cross a
+    pixel, so the sparse update takes a whole wave per pixel."""
+    rng = np.random.default_rng(6102)
+    d, rows, cols = 301, 8, 8
+    E = (rng.uniform(0.1, 1.0, size=(d, rows * cols)) *
+         (rng.uniform(size=(d, rows * cols)) < 0.25)).astype(np.float32)
+    y = rng.poisson(E @ rng.gamma(2.0, 2.0, size=rows * cols)).astype(np.float32)
+    pairs = O.neighbour_pairs(rows, cols)
+    lam_o, tr_o = O.run(E, y, np.ones(rows * cols), 0.05, pairs, 20)
+    for layout in ("sparse", "dense"):
+        lam, tr = _gpu_run(E, y, rows, cols, 0.05, 20, layout=layout, expect=layout)
+        assert (np.abs(tr - tr_o) / np.abs(tr_o)).max() < 1e-5
+        assert rel(lam, lam_o) < 1e-4
 
 
 def test_pet_tiny_penalty_root_is_stable(gpu_lib, full_problem):
@@ -121,12 +143,34 @@ def test_pet_objective_ascends(gpu_lib, full_problem, mu):
     assert fs[-1] > fs[0]
 
 
-def test_pet_graph_splits_are_bit_identical(gpu_lib, full_problem):
+@pytest.mark.parametrize("layout", ["sparse", "dense"])
+def test_pet_graph_splits_are_bit_identical(gpu_lib, full_problem, layout):
     E, y, rows, cols = full_problem
-    a, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=False)      # 16 + 4 + 2 + 1
-    b, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=True)       # 23 x 1
-    c, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=False)
+    kw = dict(layout=layout)
+    a, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=False, **kw)      # 16 + 4 + 2 + 1
+    b, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=True, **kw)       # 23 x 1
+    c, _ = _gpu_run(E, y, rows, cols, 1e-4, 23, each=False, **kw)
     assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_pet_layouts_agree(gpu_lib, full_problem):
+    E, y, rows, cols = full_problem
+    a, ta = _gpu_run(E, y, rows, cols, 1e-4, 50, each=False, layout="sparse")
+    b, tb = _gpu_run(E, y, rows, cols, 1e-4, 50, each=False, layout="dense")
+    assert rel(a, b) < 1e-5
+    assert abs(ta[-1] - tb[-1]) <= 1e-7 * abs(tb[-1])
+
+
+def test_pet_rejects_negative_or_nonfinite_data(gpu_lib):
+    from paper_1003_3272_amd import nmf
+    E, y, rows, cols = _ragged_problem()
+    for what in ("E", "y", "lam"):
+        Eb, yb, lb = E.copy(), y.copy(), np.ones(E.shape[1], np.float32)
+        {"E": Eb, "y": yb, "lam": lb}[what].flat[3] = -1.0 if what != "y" else np.nan
+        Ed, yd, ld = (torch.from_numpy(x).cuda() for x in (Eb, yb, lb))
+        with pytest.raises(nmf.NmfError) as ei:
+            nmf.Pet(Ed, yd, ld, rows, cols, 0.1)
+        assert ei.value.status == nmf.NMF_EINVAL
 
 
 def test_pet_solve_stopping_rule(gpu_lib, full_problem):
