@@ -34,10 +34,19 @@ Readings of points the paper leaves open:
   * terms with y_i = 0 contribute nothing to c (0 / 0 read as 0 for a line
     that crosses no positive intensity), and 0 ln 0 = 0 in f;
   * a pixel whose column of E is zero keeps a zero column (no scaling).
+
+solve_qn accelerates Algorithm 2 with the quasi-Newton scheme QN(q) of Zhou,
+Alexander & Lange (Table 3, columns QN(10)), the same steps as
+oracle/qn_oracle.py with the map F one iteration of Algorithm 2 on
+x = lambda and the test turned round for a maximization: the projected
+point max(x_qn, kappa F(x)) is taken when the q x q system is regular, it
+is feasible and f(x_qn) >= f(F(F(x))).
 """
 from __future__ import annotations
 
 import numpy as np
+
+from oracle import qn_oracle
 
 
 def _f64(x):
@@ -146,3 +155,79 @@ def surrogate(Es, y, lam, lam_n, mu, pairs):
         m = lam_n[j] + lam_n[k]
         pen += (2.0 * lam[j] - m) ** 2 + (2.0 * lam[k] - m) ** 2
     return q - 0.25 * mu * pen
+
+
+def rel_change(f, f_prev):
+    """The stopping statistic of Sec. 3: |f - f_prev| / (|f_prev| + 1)."""
+    return abs(f - f_prev) / (abs(f_prev) + 1.0)
+
+
+def solve(E, y, lam0, mu, pairs, max_iters, tol, check_every=1):
+    """Algorithm 2 from lam0 until the relative change of f between checks
+    (every check_every iterations) is below tol, or max_iters.  Returns
+    (lambda, iterations, f, converged)."""
+    Es = scale_columns(E)
+    lam = _f64(lam0).copy()
+    f_prev = objective(Es, y, lam, mu, pairs)
+    k = 0
+    while k < max_iters:
+        todo = min(check_every, max_iters - k)
+        for _ in range(todo):
+            lam = step(Es, y, lam, mu, pairs)
+        k += todo
+        f = objective(Es, y, lam, mu, pairs)
+        if rel_change(f, f_prev) < tol:
+            return lam, k, f, True
+        f_prev = f
+    return lam, k, f_prev, False
+
+
+def solve_qn(E, y, lam0, mu, pairs, q, max_evals, tol=None, check_every=2, kappa=0.5,
+             step_fn=None, objective_fn=None):
+    """QN(q)-accelerated Algorithm 2 from lam0, float64.  Each QN iteration
+    evaluates the map twice; the stopping rule (relative change below tol)
+    is tested on the accepted objective every check_every evaluations
+    (check_every / 2 QN iterations, at least one).  Returns (lambda, evals,
+    f, trace, accepted) with trace[0] = f(lam0) and then f after every QN
+    iteration.  step_fn(x) and objective_fn(x) replace Algorithm 2's map
+    and f (to check the scheme on maps whose fixed point is known)."""
+    Es = scale_columns(E) if E is not None else None
+    F = step_fn or (lambda v: step(Es, y, v, mu, pairs))
+    obj = objective_fn or (lambda v: objective(Es, y, v, mu, pairs))
+    x = _f64(lam0).copy()
+    f = obj(x)
+    trace = [f]
+    Us, Vs = [], []
+    evals = accepted = it = 0
+    chunk = max(1, check_every // 2)
+    f_prev = f
+    while evals + 2 <= max_evals:
+        x1 = F(x)
+        x2 = F(x1)
+        evals += 2
+        Us.append(x1 - x)
+        Vs.append(x2 - x1)
+        if len(Us) > q:
+            Us.pop(0)
+            Vs.pop(0)
+        f2 = obj(x2)
+        xq = qn_oracle.qn_step(np.stack(Us, axis=1), np.stack(Vs, axis=1), x, x1)
+        if xq is not None and kappa > 0.0:
+            xq = qn_oracle.project(xq, x1, kappa)
+        take = False
+        if xq is not None and qn_oracle.feasible(xq, x1):
+            fq = obj(xq)
+            take = fq >= f2
+        if take:
+            x, f = xq, fq
+            accepted += 1
+        else:
+            x, f = x2, f2
+        trace.append(f)
+        it += 1
+        if tol is not None and it % chunk == 0:
+            done = rel_change(f, f_prev) < tol
+            f_prev = f
+            if done:
+                break
+    return x, evals, f, np.array(trace), accepted
