@@ -360,7 +360,8 @@ def pet_experiment(args, log):
     a 64 x 64 image, 2016 lines of flight.  Per iteration: the time of a long
     replayed window (no checks), and, for each roughness constant, the
     solve under the paper's stopping rule (relative change of f below 1e-9,
-    checked every iteration, at most --pet-max-iters iterations).  The
+    checked every iteration, at most --pet-max-iters iterations), plain and
+    accelerated by QN(10) (the rule checked every QN iteration).  The
     oracle's float64 iteration is timed on a few iterations for the CPU
     figure."""
     import torch
@@ -397,10 +398,23 @@ def pet_experiment(args, log):
             t = time.perf_counter()
             conv, iters, f = m.solve(args.pet_max_iters, tol=1e-9, check_every=1)
             el = time.perf_counter() - t
+        ld = torch.ones(p, dtype=torch.float32, device="cuda")
+        with nmf.Pet(Ed, yd, ld, 64, 64, mu) as m:
+            m.solve_qn(4, q=10, tol=0.0)     # QN graph captured and warm
+            ld.fill_(1.0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            qconv, qev, qacc, qf, _ = m.solve_qn(min(2 * args.pet_max_iters, 131072), q=10, tol=1e-9,
+                                                 check_every=2)
+            qel = time.perf_counter() - t
         out["mus"][repr(mu)] = {"us_per_iter": round(it_us, 2), "solve_s": round(el, 4),
-                                "iters": iters, "converged": conv, "f": f}
+                                "iters": iters, "converged": conv, "f": f,
+                                "qn10": {"solve_s": round(qel, 4), "evals": qev,
+                                         "qn_iters": qev // 2, "accepted": qacc,
+                                         "converged": qconv, "f": qf}}
         log(f"pet mu={mu}: {it_us:.1f} us/iter, solve {iters} iters in {el:.3f} s "
-            f"({'converged' if conv else 'cap'}), f={f:.10g}")
+            f"({'converged' if conv else 'cap'}), f={f:.10g}; QN(10) {qev // 2} QN iterations "
+            f"({qev} maps) in {qel:.3f} s, f={qf:.10g}")
     # one iteration reads the nonzeros of E_s twice (by lines, by pixels) as
     # (float32 value, int32 index) pairs, and gathers lambda and the ratios
     nnz = out["nnz_E"]

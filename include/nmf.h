@@ -180,7 +180,7 @@ nmf_status nmf_solve(nmf_ctx* ctx, int32_t max_iters, int32_t* iters_done_host,
    at least one).  *iters_done_host: evaluations of F run; *accepted_host
    (may be NULL): QN iterations whose extrapolated point was taken; *f_host:
    the objective of the factors left in W and H; trace_host (may be NULL):
-   f_0 and then the objective after every QN iteration.  1 <= q <= 8.
+   f_0 and then the objective after every QN iteration.  1 <= q <= 16.
    NMF_EUNSUPPORTED for the Poisson loss.  Returns as nmf_solve. */
 nmf_status nmf_solve_qn(nmf_ctx* ctx, int32_t q, int32_t max_iters,
                         int32_t* iters_done_host, int32_t* accepted_host,
@@ -478,6 +478,26 @@ nmf_status nmf_pet_objective(nmf_pet* m, double* f_host);
    Returns NMF_OK, NMF_ENOTCONVERGED at the cap, NMF_ENONFINITE. */
 nmf_status nmf_pet_solve(nmf_pet* m, int32_t max_iters, double tol, int32_t check_every,
                          int32_t* iters_done_host, double* f_host);
+
+/* nmf_pet_solve accelerated by QN(q) (Zhou, Alexander & Lange; the QN(10)
+   columns of Table 3), as nmf_solve_qn does for NMF: with F one iteration
+   of Algorithm 2, each QN iteration evaluates F twice, keeps the secant
+   pairs of the last q QN iterations in float64, forms the quasi-Newton
+   point x_qn = F(x) + V (U^T U - U^T V)^-1 U^T (F(x) - x), projects it onto
+   lambda >= 0.5 F(x) entrywise, and takes it when the q x q system is
+   regular and f(x_qn) >= f(F(F(x))); otherwise it keeps F(F(x)).  So f
+   never decreases.  Every decision is made on the device; one QN iteration
+   is replayed from a HIP graph.  max_evals counts evaluations of F (two per
+   QN iteration, at most 131072); the rule |f - f_prev| / (|f_prev| + 1) <
+   tol is tested on the accepted objective every check_every evaluations
+   (check_every / 2 QN iterations, at least one).  *evals_done: evaluations
+   of F run; *accepted (may be NULL): QN iterations whose point was taken;
+   *f_host: f of the intensities left in lambda; trace (may be NULL): f of
+   the start and then after every QN iteration, up to trace_len entries.
+   1 <= q <= 16.  Returns NMF_OK, NMF_ENOTCONVERGED, NMF_ENONFINITE. */
+nmf_status nmf_pet_solve_qn(nmf_pet* m, int32_t q, int32_t max_evals, double tol,
+                            int32_t check_every, int32_t* evals_done, int32_t* accepted,
+                            double* f_host, double* trace, int32_t trace_len);
 
 /* Release the object (not the caller's lambda).  NULL is ignored. */
 void nmf_pet_destroy(nmf_pet* m);

@@ -327,11 +327,12 @@ __device__ __forceinline__ double line_term(float y, double b) {
 }
 
 // part[i] = y_i ln B_i - B_i (B_i in float64) for the lines, then the
-// penalty parts; one wave per line, then one wave per 64 pixels.
+// penalty parts, each times sign (+1, or -1 for the quasi-Newton test, which
+// minimizes); one wave per line, then one wave per 64 pixels.
 __global__ __launch_bounds__(256) void k_pet_objective(const float* __restrict__ Es, int64_t d,
                                                        int64_t p, const float* __restrict__ lam,
                                                        const float* __restrict__ y, int rows,
-                                                       int cols, double mu,
+                                                       int cols, double mu, double sign,
                                                        double* __restrict__ part) {
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -340,17 +341,17 @@ __global__ __launch_bounds__(256) void k_pet_objective(const float* __restrict__
     double s = 0.0;
     for (int64_t j = lane; j < p; j += 64) s = fma((double)row[j], (double)lam[j], s);
     s = wave_sum_d(s);
-    if (lane == 0) part[w] = line_term(y[w], s);
+    if (lane == 0) part[w] = sign * line_term(y[w], s);
   } else if (w < d + (p + 63) / 64) {
     const int64_t j = (w - d) * 64 + lane;
-    if (j < p) part[d + j] = pet_penalty_part(lam, j, rows, cols, mu);
+    if (j < p) part[d + j] = sign * pet_penalty_part(lam, j, rows, cols, mu);
   }
 }
 
 __global__ __launch_bounds__(256) void k_pet_objective_ell(
     const float* __restrict__ val, const int32_t* __restrict__ idx, const int32_t* __restrict__ cnt,
     int64_t wr, int64_t d, int64_t p, const float* __restrict__ lam, const float* __restrict__ y,
-    int rows, int cols, double mu, double* __restrict__ part) {
+    int rows, int cols, double mu, double sign, double* __restrict__ part) {
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w < d) {
@@ -360,11 +361,19 @@ __global__ __launch_bounds__(256) void k_pet_objective_ell(
     double s = 0.0;
     for (int k = lane; k < n; k += 64) s = fma((double)v[k], (double)lam[ix[k]], s);
     s = wave_sum_d(s);
-    if (lane == 0) part[w] = line_term(y[w], s);
+    if (lane == 0) part[w] = sign * line_term(y[w], s);
   } else if (w < d + (p + 63) / 64) {
     const int64_t j = (w - d) * 64 + lane;
-    if (j < p) part[d + j] = pet_penalty_part(lam, j, rows, cols, mu);
+    if (j < p) part[d + j] = sign * pet_penalty_part(lam, j, rows, cols, mu);
   }
+}
+
+// The quasi-Newton decision taken (st[4]): lambda = xq.
+__global__ void k_pet_qn_commit(const int32_t* __restrict__ st, const float* __restrict__ xq,
+                                float* __restrict__ lam, int64_t p) {
+  if (st[4] == 0) return;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < p; j += (int64_t)gridDim.x * 256)
+    lam[j] = xq[j];
 }
 
 unsigned pblocks(int64_t total, int64_t cap = 65535) {
@@ -373,6 +382,8 @@ unsigned pblocks(int64_t total, int64_t cap = 65535) {
 }
 
 constexpr int kPetGraphs = 5;  // graphs of 1, 2, 4, 8 and 16 iterations
+constexpr int32_t kPetQnCap = 65536;  // QN iterations recorded per solve
+constexpr float kPetQnKappa = 0.5f;   // projection lambda >= kappa F(lambda)
 
 }  // namespace
 
@@ -399,6 +410,17 @@ struct nmf_pet {
   double* hostbuf_dev = nullptr;  // the same memory as the device addresses it
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gp[kPetGraphs] = {};
+  // QN(q)
+  int qn_q = 0;
+  void* qn_ws = nullptr;
+  size_t qn_bytes = 0;
+  float *qx0 = nullptr, *qxq = nullptr;
+  double *qU = nullptr, *qV = nullptr, *qdpart = nullptr, *qGUU = nullptr, *qGUV = nullptr;
+  double *qcoef = nullptr, *qf = nullptr;
+  int32_t* qst = nullptr;
+  double* qfout = nullptr;      // pinned, coherent: -f after every QN iteration
+  double* qfout_dev = nullptr;  // its device-side address
+  hipGraphExec_t qn_graph = nullptr;
 };
 
 namespace {
@@ -407,6 +429,15 @@ namespace {
   do {                                              \
     if ((expr) != hipSuccess) return NMF_EDEVICE;   \
   } while (0)
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
 
 nmf_status pet_iter(nmf_pet* m, const float* src, float* dst) {
   const unsigned lines = (unsigned)((m->d + 3) / 4);
@@ -477,20 +508,124 @@ nmf_status pet_capture(nmf_pet* m, int iters, hipGraphExec_t* out) {
   return s;
 }
 
-nmf_status pet_objective_sync(nmf_pet* m, double* f) {
+// sign * f(lam) into out (device-visible address), in a fixed order.
+nmf_status pet_objective_enqueue(nmf_pet* m, const float* lam, double sign, double* out) {
   const int64_t waves = m->d + (m->p + 63) / 64;
   const unsigned blocks = (unsigned)((waves + 3) / 4);
   if (m->sparse)
     hipLaunchKernelGGL(k_pet_objective_ell, dim3(blocks), dim3(256), 0, m->st, m->rval, m->ridx,
-                       m->rowcnt, m->wr, m->d, m->p, m->lam, m->y, m->rows, m->cols, m->mu_d,
+                       m->rowcnt, m->wr, m->d, m->p, lam, m->y, m->rows, m->cols, m->mu_d, sign,
                        m->part);
   else
-    hipLaunchKernelGGL(k_pet_objective, dim3(blocks), dim3(256), 0, m->st, m->Es, m->d, m->p,
-                       m->lam, m->y, m->rows, m->cols, m->mu_d, m->part);
+    hipLaunchKernelGGL(k_pet_objective, dim3(blocks), dim3(256), 0, m->st, m->Es, m->d, m->p, lam,
+                       m->y, m->rows, m->cols, m->mu_d, sign, m->part);
   PTRY_HIP(hipGetLastError());
-  PTRY_HIP(launch_reduce_f64(m->part, m->d + m->p, m->hostbuf_dev, m->st));
+  PTRY_HIP(launch_reduce_f64(m->part, m->d + m->p, out, m->st));
+  return NMF_OK;
+}
+
+nmf_status pet_objective_sync(nmf_pet* m, double* f) {
+  nmf_status s = pet_objective_enqueue(m, m->lam, 1.0, m->hostbuf_dev);
+  if (s != NMF_OK) return s;
   PTRY_HIP(hipStreamSynchronize(m->st));
   *f = m->hostbuf[0];
+  return NMF_OK;
+}
+
+// One QN iteration (Zhou, Alexander & Lange), every decision on the device:
+// x0 = lambda; x1 = F(x0) (in lam2); x2 = F(x1) (in lambda); the secant pair
+// (x1 - x0, x2 - x1) enters the float64 rings; xq = max(x1 + V c, kappa x1);
+// -f(x2) and -f(xq) are compared (the shared selection minimizes); lambda =
+// xq when taken.
+nmf_status pet_qn_enqueue(nmf_pet* m) {
+  const int64_t D = m->p;
+  const int q = m->qn_q;
+  PTRY_HIP(launch_qn_copy(m->lam, m->qx0, D, m->st));
+  nmf_status s = pet_iter(m, m->lam, m->lam2);
+  if (s == NMF_OK) s = pet_iter(m, m->lam2, m->lam);
+  if (s != NMF_OK) return s;
+  PTRY_HIP(launch_qn_pairs(m->qx0, m->lam2, m->lam, m->qU, m->qV, D, q, m->qst, m->st));
+  PTRY_HIP(launch_qn_dots_solve(m->qU, m->qV, D, q, m->qst, m->qdpart, m->qGUU, m->qGUV, m->qcoef,
+                                m->st));
+  PTRY_HIP(launch_qn_combine(m->lam2, m->qV, m->qcoef, D, q, kPetQnKappa, m->qst, m->qxq, m->st));
+  s = pet_objective_enqueue(m, m->lam, -1.0, m->qf + 0);
+  if (s == NMF_OK) s = pet_objective_enqueue(m, m->qxq, -1.0, m->qf + 1);
+  if (s != NMF_OK) return s;
+  PTRY_HIP(launch_qn_select(m->qf, m->qst, m->qfout_dev, kPetQnCap, m->st));
+  hipLaunchKernelGGL(k_pet_qn_commit, dim3(pblocks(D, 1024)), dim3(256), 0, m->st, m->qst, m->qxq,
+                     m->lam, D);
+  PTRY_HIP(hipGetLastError());
+  return NMF_OK;
+}
+
+// QN workspace (kept while q is unchanged) and its graph; the history is
+// cleared on every call.
+nmf_status pet_qn_prepare(nmf_pet* m, int q) {
+  const int64_t D = m->p;
+  const int qm = qn_max_q();
+  if (m->qn_q != q || !m->qn_ws) {
+    if (m->qn_graph) (void)hipGraphExecDestroy(m->qn_graph);
+    m->qn_graph = nullptr;
+    if (m->qn_ws) (void)hipFree(m->qn_ws);
+    m->qn_ws = nullptr;
+    Carver a;
+    const size_t ox0 = a.take(4 * (size_t)D), oxq = a.take(4 * (size_t)D);
+    const size_t oU = a.take(8 * (size_t)q * D), oV = a.take(8 * (size_t)q * D);
+    const size_t odp = a.take(8 * (size_t)qn_dot_blocks() * 3 * q);
+    const size_t oguu = a.take(8 * (size_t)qm * qm), oguv = a.take(8 * (size_t)qm * qm);
+    const size_t oc = a.take(8 * (size_t)qm), of = a.take(8 * 2), ost = a.take(4 * 8);
+    if (hipMalloc(&m->qn_ws, a.off) != hipSuccess) {
+      m->qn_ws = nullptr;
+      (void)hipGetLastError();
+      return NMF_ENOMEM;
+    }
+    m->qn_bytes = a.off;
+    char* b = static_cast<char*>(m->qn_ws);
+    m->qx0 = reinterpret_cast<float*>(b + ox0);
+    m->qxq = reinterpret_cast<float*>(b + oxq);
+    m->qU = reinterpret_cast<double*>(b + oU);
+    m->qV = reinterpret_cast<double*>(b + oV);
+    m->qdpart = reinterpret_cast<double*>(b + odp);
+    m->qGUU = reinterpret_cast<double*>(b + oguu);
+    m->qGUV = reinterpret_cast<double*>(b + oguv);
+    m->qcoef = reinterpret_cast<double*>(b + oc);
+    m->qf = reinterpret_cast<double*>(b + of);
+    m->qst = reinterpret_cast<int32_t*>(b + ost);
+    m->qn_q = q;
+    if (!m->qfout) {
+      if (hipHostMalloc(reinterpret_cast<void**>(&m->qfout), sizeof(double) * kPetQnCap,
+                        hipHostMallocCoherent) != hipSuccess) {
+        m->qfout = nullptr;
+        (void)hipGetLastError();
+        return NMF_ENOMEM;
+      }
+      PTRY_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&m->qfout_dev), m->qfout, 0));
+    }
+  }
+  PTRY_HIP(launch_fill_u32(static_cast<uint32_t*>(m->qn_ws), (int64_t)(m->qn_bytes / 4), 0u,
+                           m->st));
+  if (!m->qn_graph) {
+    if (!m->cap_stream) PTRY_HIP(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+    PTRY_HIP(hipStreamSynchronize(m->st));
+    hipStream_t user = m->st;
+    m->st = m->cap_stream;
+    hipGraph_t graph = nullptr;
+    nmf_status s = NMF_OK;
+    if (hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      s = NMF_EDEVICE;
+    if (s == NMF_OK) {
+      s = pet_qn_enqueue(m);
+      const hipError_t e = hipStreamEndCapture(m->cap_stream, &graph);
+      if (s == NMF_OK && (e != hipSuccess || !graph)) s = NMF_EDEVICE;
+    }
+    m->st = user;
+    if (s == NMF_OK && (hipGraphInstantiate(&m->qn_graph, graph, nullptr, nullptr, 0) !=
+                            hipSuccess ||
+                        hipGraphUpload(m->qn_graph, m->st) != hipSuccess))
+      s = NMF_EDEVICE;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (s != NMF_OK) return s;
+  }
   return NMF_OK;
 }
 
@@ -498,21 +633,15 @@ void pet_free(nmf_pet* m) {
   if (!m) return;
   for (hipGraphExec_t g : m->gp)
     if (g) (void)hipGraphExecDestroy(g);
+  if (m->qn_graph) (void)hipGraphExecDestroy(m->qn_graph);
+  if (m->qn_ws) (void)hipFree(m->qn_ws);
+  if (m->qfout) (void)hipHostFree(m->qfout);
   if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
   if (m->ws_e) (void)hipFree(m->ws_e);
   if (m->ws) (void)hipFree(m->ws);
   if (m->hostbuf) (void)hipHostFree(m->hostbuf);
   delete m;
 }
-
-struct Carver {
-  size_t off = 0;
-  size_t take(size_t bytes) {
-    const size_t o = off;
-    off += (bytes + 255) / 256 * 256;
-    return o;
-  }
-};
 
 // Workspace, validation, counts and the layout of E_s.  Synchronizes.
 nmf_status pet_setup(nmf_pet* m, const float* E, const float* y, int32_t layout) {
@@ -697,6 +826,58 @@ nmf_status nmf_pet_solve(nmf_pet* m, int32_t max_iters, double tol, int32_t chec
     if (done) return NMF_OK;
   }
   return NMF_ENOTCONVERGED;
+}
+
+nmf_status nmf_pet_solve_qn(nmf_pet* m, int32_t q, int32_t max_evals, double tol,
+                            int32_t check_every, int32_t* evals_done, int32_t* accepted,
+                            double* f_host, double* trace, int32_t trace_len) {
+  if (!m || !evals_done || !f_host || q < 1 || max_evals < 0 || check_every < 1 ||
+      !(tol >= 0.0) || (trace && trace_len < 0))
+    return NMF_EINVAL;
+  if (q > qn_max_q() || max_evals / 2 > kPetQnCap) return NMF_EINVAL;
+  *evals_done = 0;
+  if (accepted) *accepted = 0;
+  double f_prev;
+  nmf_status s = nmf_pet_objective(m, &f_prev);
+  *f_host = f_prev;
+  if (s != NMF_OK) return s;
+  int32_t nt = 0;
+  if (trace && nt < trace_len) trace[nt++] = f_prev;
+  s = pet_qn_prepare(m, q);
+  if (s != NMF_OK) return s;
+  // chunks of check_every map evaluations (check_every / 2 QN iterations,
+  // at least one); the rule is tested on the accepted objective at the end
+  // of each chunk
+  const int32_t chunk = std::max<int32_t>(1, check_every / 2);
+  const int32_t total = max_evals / 2;
+  int32_t it = 0;
+  bool done = false;
+  double f = f_prev;
+  while (!done && it < total) {
+    const int32_t todo = std::min(chunk, total - it);
+    for (int32_t k = 0; k < todo; ++k) PTRY_HIP(hipGraphLaunch(m->qn_graph, m->st));
+    PTRY_HIP(hipStreamSynchronize(m->st));
+    for (int32_t k = it; k < it + todo; ++k)
+      if (trace && nt < trace_len) trace[nt++] = -m->qfout[k];
+    it += todo;
+    f = -m->qfout[it - 1];
+    if (!std::isfinite(f)) {
+      s = NMF_ENONFINITE;
+      break;
+    }
+    done = std::fabs(f - f_prev) / (std::fabs(f_prev) + 1.0) < tol;
+    f_prev = f;
+  }
+  *evals_done = 2 * it;
+  *f_host = f;
+  if (accepted) {
+    int32_t* st = reinterpret_cast<int32_t*>(m->hostbuf);  // pinned
+    PTRY_HIP(hipMemcpyAsync(st, m->qst, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, m->st));
+    PTRY_HIP(hipStreamSynchronize(m->st));
+    *accepted = st[1];
+  }
+  if (s != NMF_OK) return s;
+  return done ? NMF_OK : NMF_ENOTCONVERGED;
 }
 
 void nmf_pet_destroy(nmf_pet* m) {

@@ -24,7 +24,7 @@
 namespace nmfk {
 namespace {
 
-constexpr int kQnMax = 8;       // largest q
+constexpr int kQnMax = 16;      // largest q
 constexpr int kDotBlocks = 256;  // partial-sum blocks of the dot products
 
 // st[0]: QN iterations done; st[1]: accepted; st[2]: regular system;
@@ -45,12 +45,14 @@ __global__ void k_qn_pairs(const float* __restrict__ x0, const float* __restrict
 }
 
 // Partial sums (per block, fixed order) of u_s . u_j, u_s . v_j and
-// u_j . v_s for every slot j < q: dpart[block][3 q].
+// u_j . v_s for every slot j < q: dpart[block][3 q].  Each wave reduces its
+// 3q sums with lane shuffles; thread k < 3q then adds the four waves' sums
+// in wave order.
 __global__ __launch_bounds__(256) void k_qn_dots(const double* __restrict__ U,
                                                  const double* __restrict__ V, int64_t D, int q,
                                                  const int32_t* __restrict__ st,
                                                  double* __restrict__ dpart) {
-  __shared__ double sh[256];
+  __shared__ double sh[4][3 * kQnMax];
   const int s = st[0] % q;
   const double* us = U + (int64_t)s * D;
   const double* vs = V + (int64_t)s * D;
@@ -70,87 +72,120 @@ __global__ __launch_bounds__(256) void k_qn_dots(const double* __restrict__ U,
       }
     }
   }
-  for (int k = 0; k < 3 * q; ++k) {
-    double val = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int kk = 0; kk < 3 * kQnMax; ++kk)
-      if (kk == k) val = acc[kk];
-    sh[threadIdx.x] = val;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
+  for (int k = 0; k < 3 * kQnMax; ++k) {
+    if (k < 3 * q) {
+      double v = acc[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) sh[wave][k] = v;
     }
-    if (threadIdx.x == 0) dpart[(int64_t)blockIdx.x * 3 * q + k] = sh[0];
-    __syncthreads();
   }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 3 * q)
+    dpart[(int64_t)blockIdx.x * 3 * q + t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
 }
 
-// One thread: finish the dot products (blocks in order), update the slot's
-// row and column of U^T U (symmetric) and U^T V, then solve
-// (U^T U - U^T V) c = U^T u_s over the filled slots by Gaussian elimination
-// with partial pivoting.  A pivot below 1e-12 of the largest |entry| marks
-// the system singular (c = 0, st[2] = 0).  Clears st[3] for the combine.
-__global__ void k_qn_solve(const double* __restrict__ dpart, int nblocks, int q,
-                           int32_t* __restrict__ st, double* __restrict__ GUU,
-                           double* __restrict__ GUV, double* __restrict__ coef) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// One wave: thread t < 3q finishes dot product t (blocks in order); the
+// slot's row and column of U^T U (symmetric) and U^T V are updated; then
+// (U^T U - U^T V) c = U^T u_s is solved over the filled slots by Gaussian
+// elimination with partial pivoting, the matrix in LDS and each elimination
+// step spread over the lanes.  A pivot below 1e-12 of the largest |entry|
+// marks the system singular (c = 0, st[2] = 0).  Clears st[3] for the
+// combine.
+__global__ __launch_bounds__(64) void k_qn_solve(const double* __restrict__ dpart, int nblocks,
+                                                 int q, int32_t* __restrict__ st,
+                                                 double* __restrict__ GUU,
+                                                 double* __restrict__ GUV,
+                                                 double* __restrict__ coef) {
+  __shared__ double dots[3 * kQnMax];
+  __shared__ double A[kQnMax][kQnMax + 1];
+  __shared__ double fct[kQnMax];
+  __shared__ double x[kQnMax];
+  __shared__ int piv_s, ok_s;
+  if (blockIdx.x != 0) return;
+  const int t = threadIdx.x;
   const int s = st[0] % q;
   const int m = st[0] + 1 < q ? st[0] + 1 : q;  // filled slots: 0 .. m - 1
-  for (int j = 0; j < q; ++j) {
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int k = 0; k < nblocks; ++k) {
-      a += dpart[(int64_t)k * 3 * q + 3 * j + 0];
-      b += dpart[(int64_t)k * 3 * q + 3 * j + 1];
-      c += dpart[(int64_t)k * 3 * q + 3 * j + 2];
-    }
-    GUU[s * kQnMax + j] = a;
-    GUU[j * kQnMax + s] = a;
-    GUV[s * kQnMax + j] = b;
-    GUV[j * kQnMax + s] = c;
+  if (t < 3 * q) {
+    double a = 0.0;
+    for (int k = 0; k < nblocks; ++k) a += dpart[(int64_t)k * 3 * q + t];
+    dots[t] = a;
   }
-  double A[kQnMax][kQnMax + 1];
+  __syncthreads();
+  if (t < q) {
+    const double a = dots[3 * t + 0], b = dots[3 * t + 1], c = dots[3 * t + 2];
+    GUU[s * kQnMax + t] = a;
+    GUU[t * kQnMax + s] = a;
+    GUV[s * kQnMax + t] = b;
+    GUV[t * kQnMax + s] = c;
+  }
+  // the system, with row and column s taken from the fresh dot products
+  // (the entries stored above are read by later launches only)
   double amax = 0.0;
-  for (int i = 0; i < m; ++i) {
-    for (int j = 0; j < m; ++j) {
-      A[i][j] = GUU[i * kQnMax + j] - GUV[i * kQnMax + j];
-      amax = fmax(amax, fabs(A[i][j]));
+  for (int idx = t; idx < m * (m + 1); idx += 64) {
+    const int i = idx / (m + 1), j = idx % (m + 1);
+    double v;
+    if (j == m) {
+      v = dots[3 * i + 0];  // (U^T u_s)_i = u_i . u_s
+    } else {
+      if (i == s)
+        v = dots[3 * j + 0] - dots[3 * j + 1];  // u_s . u_j - u_s . v_j
+      else if (j == s)
+        v = dots[3 * i + 0] - dots[3 * i + 2];  // u_i . u_s - u_i . v_s
+      else
+        v = GUU[i * kQnMax + j] - GUV[i * kQnMax + j];
+      amax = fmax(amax, fabs(v));
     }
-    A[i][m] = GUU[i * kQnMax + s];  // U^T u_s
+    A[i][j] = v;
   }
-  int ok = amax > 0.0 && isfinite(amax);
-  for (int col = 0; col < m && ok; ++col) {
-    int piv = col;
-    for (int i = col + 1; i < m; ++i)
-      if (fabs(A[i][col]) > fabs(A[piv][col])) piv = i;
-    if (!(fabs(A[piv][col]) > 1e-12 * amax)) {
-      ok = 0;
-      break;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  if (t == 0) ok_s = amax > 0.0 && isfinite(amax);
+  __syncthreads();
+  for (int col = 0; col < m; ++col) {
+    if (!ok_s) break;  // uniform: read after a barrier
+    if (t == 0) {
+      int piv = col;
+      for (int i = col + 1; i < m; ++i)
+        if (fabs(A[i][col]) > fabs(A[piv][col])) piv = i;
+      piv_s = piv;
+      if (!(fabs(A[piv][col]) > 1e-12 * amax)) ok_s = 0;
     }
-    if (piv != col)
-      for (int j = col; j <= m; ++j) {
-        const double t = A[col][j];
-        A[col][j] = A[piv][j];
-        A[piv][j] = t;
+    __syncthreads();
+    if (!ok_s) break;
+    const int piv = piv_s;
+    if (piv != col && t >= col && t <= m) {
+      const double tmp = A[col][t];
+      A[col][t] = A[piv][t];
+      A[piv][t] = tmp;
+    }
+    __syncthreads();
+    if (t > col && t < m) fct[t] = A[t][col] / A[col][col];
+    __syncthreads();
+    for (int idx = t; idx < (m - col - 1) * (m - col); idx += 64) {
+      const int i = col + 1 + idx / (m - col), j = col + 1 + idx % (m - col);
+      A[i][j] -= fct[i] * A[col][j];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    int ok = ok_s;
+    for (int i = 0; i < kQnMax; ++i) x[i] = 0.0;
+    if (ok) {
+      for (int i = m - 1; i >= 0; --i) {
+        double v = A[i][m];
+        for (int j = i + 1; j < m; ++j) v -= A[i][j] * x[j];
+        x[i] = v / A[i][i];
       }
-    for (int i = col + 1; i < m; ++i) {
-      const double fct = A[i][col] / A[col][col];
-      for (int j = col; j <= m; ++j) A[i][j] -= fct * A[col][j];
+      for (int i = 0; i < m; ++i) ok = ok && isfinite(x[i]);
     }
+    for (int j = 0; j < kQnMax; ++j) coef[j] = ok ? x[j] : 0.0;
+    st[2] = ok;
+    st[3] = 0;
   }
-  double x[kQnMax];
-  for (int i = 0; i < kQnMax; ++i) x[i] = 0.0;
-  if (ok) {
-    for (int i = m - 1; i >= 0; --i) {
-      double t = A[i][m];
-      for (int j = i + 1; j < m; ++j) t -= A[i][j] * x[j];
-      x[i] = t / A[i][i];
-    }
-    for (int i = 0; i < m; ++i) ok = ok && isfinite(x[i]);
-  }
-  for (int j = 0; j < kQnMax; ++j) coef[j] = ok ? x[j] : 0.0;
-  st[2] = ok;
-  st[3] = 0;
 }
 
 // xq = max(x1 + sum_j c_j v_j, kappa x1) in float64, rounded to float32 (x1
@@ -257,9 +292,10 @@ hipError_t launch_qn_dots_solve(const double* U, const double* V, int64_t D, int
                                 int32_t* state, double* dpart, double* GUU, double* GUV,
                                 double* coef, hipStream_t st) {
   if (q < 1 || q > kQnMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_qn_dots, dim3(kDotBlocks), dim3(256), 0, st, U, V, D, q, state, dpart);
-  hipLaunchKernelGGL(k_qn_solve, dim3(1), dim3(64), 0, st, dpart, kDotBlocks, q, state, GUU, GUV,
-                     coef);
+  const unsigned blocks = qblocks(D, kDotBlocks);  // at most kDotBlocks rows of dpart
+  hipLaunchKernelGGL(k_qn_dots, dim3(blocks), dim3(256), 0, st, U, V, D, q, state, dpart);
+  hipLaunchKernelGGL(k_qn_solve, dim3(1), dim3(64), 0, st, dpart, (int)blocks, q, state, GUU,
+                     GUV, coef);
   return hipGetLastError();
 }
 

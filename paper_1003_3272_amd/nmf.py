@@ -164,6 +164,10 @@ def load(path: str = LIB_PATH):
     lib.nmf_pet_solve.argtypes = [P, c_int32, c_double, c_int32, POINTER(c_int32),
                                   POINTER(c_double)]
     lib.nmf_pet_solve.restype = c_int32
+    lib.nmf_pet_solve_qn.argtypes = [P, c_int32, c_int32, c_double, c_int32, POINTER(c_int32),
+                                     POINTER(c_int32), POINTER(c_double), POINTER(c_double),
+                                     c_int32]
+    lib.nmf_pet_solve_qn.restype = c_int32
     lib.nmf_pet_destroy.argtypes = [P]
     lib.nmf_pet_destroy.restype = None
     lib.nmf_strerror.argtypes = [c_int32]
@@ -652,6 +656,18 @@ class Pet:
                                               int(check_every), byref(it), byref(f)),
                          "nmf_pet_solve")
         return st == NMF_OK, it.value, f.value
+
+    def solve_qn(self, max_evals, q=10, tol=1e-9, check_every=2, trace_len=0):
+        """QN(q)-accelerated solve; returns (converged, evaluations,
+        accepted, f, trace)."""
+        ev, acc, f = c_int32(), c_int32(), c_double()
+        tr = (c_double * max(trace_len, 1))()
+        st = self._check(load().nmf_pet_solve_qn(self._m, int(q), int(max_evals), float(tol),
+                                                 int(check_every), byref(ev), byref(acc),
+                                                 byref(f), tr if trace_len > 0 else None,
+                                                 int(trace_len)), "nmf_pet_solve_qn")
+        n = min(trace_len, 1 + ev.value // 2)
+        return st == NMF_OK, ev.value, acc.value, f.value, list(tr[:n])
 
     def close(self):
         if self._m:

@@ -202,3 +202,70 @@ def test_pet_start_is_the_callers(gpu_lib):
     lam_o, tr_o = O.run(E, y, lam0, 1e-2, pairs, 3)
     assert abs(tr[0] - tr_o[0]) <= 1e-6 * max(abs(tr_o[0]), 1.0)
     assert rel(lam, lam_o) < 1e-5
+
+
+# ---- QN(q) acceleration (Table 3, QN(10) columns) -----------------------------
+
+def test_pet_qn_first_iterations_match_oracle(gpu_lib, full_problem):
+    """QN(10) from lambda = 1 at mu = 1e-5: the accepted objective after
+    each of the first 6 QN iterations within 1e-6 relative of the float64
+    oracle's (later iterations depend on ill-conditioned secant systems and
+    are compared through their limit instead)."""
+    from paper_1003_3272_amd import nmf
+    E, y, rows, cols = full_problem
+    pairs = O.neighbour_pairs(rows, cols)
+    _, _, _, tr_o, acc_o = O.solve_qn(E, y, np.ones(E.shape[1]), 1e-5, pairs, 10, 12)
+    Ed, yd = torch.from_numpy(E).cuda(), torch.from_numpy(y).cuda()
+    ld = torch.ones(E.shape[1], dtype=torch.float32, device="cuda")
+    with nmf.Pet(Ed, yd, ld, rows, cols, 1e-5) as m:
+        conv, ev, acc, f, tr = m.solve_qn(12, q=10, tol=0.0, trace_len=7)
+    assert ev == 12 and len(tr) == 7
+    err = np.abs(np.array(tr) - tr_o[:7]) / np.abs(tr_o[:7])
+    assert err.max() < 1e-6, err
+    assert abs(acc - acc_o) <= 1
+
+
+@pytest.mark.parametrize("mu", [1e-5, 1e-3])
+def test_pet_qn_reaches_the_maximum_in_fewer_evaluations(gpu_lib, full_problem, mu):
+    """To the stopping rule at 1e-10, QN(10) needs far fewer map evaluations
+    than plain MM and ends at an objective no lower (f is concave, so both
+    approach the same maximum; the slower MM stops further below it)."""
+    from paper_1003_3272_amd import nmf
+    E, y, rows, cols = full_problem
+    Ed, yd = torch.from_numpy(E).cuda(), torch.from_numpy(y).cuda()
+    res = {}
+    for kind in ("mm", "qn"):
+        ld = torch.ones(E.shape[1], dtype=torch.float32, device="cuda")
+        with nmf.Pet(Ed, yd, ld, rows, cols, mu) as m:
+            if kind == "mm":
+                conv, it, f = m.solve(100000, tol=1e-10, check_every=1)
+                res[kind] = (conv, it, f)
+            else:
+                conv, ev, acc, f, tr = m.solve_qn(100000, q=10, tol=1e-10, check_every=2,
+                                                  trace_len=100001)
+                res[kind] = (conv, ev, f)
+                tr = np.array(tr)
+                assert (np.diff(tr) >= -1e-6 * np.abs(tr[1:])).all()
+                assert acc > 0
+                assert f == m.objective()
+    assert res["mm"][0] and res["qn"][0]
+    assert res["qn"][1] < res["mm"][1] / 2, res
+    assert res["qn"][2] >= res["mm"][2] - 1e-7 * abs(res["mm"][2]), res
+
+
+def test_pet_qn_then_plain_steps_continue(gpu_lib):
+    from paper_1003_3272_amd import nmf
+    E, y, rows, cols = _ragged_problem()
+    Ed, yd = torch.from_numpy(E).cuda(), torch.from_numpy(y).cuda()
+    ld = torch.ones(E.shape[1], dtype=torch.float32, device="cuda")
+    pairs = O.neighbour_pairs(rows, cols)
+    with nmf.Pet(Ed, yd, ld, rows, cols, 1e-2) as m:
+        conv, ev, acc, f, _ = m.solve_qn(40, q=4, tol=0.0)
+        lam_after = ld.cpu().numpy()
+        assert abs(O.objective(O.scale_columns(E), y, lam_after, 1e-2, pairs) - f) <= 1e-6 * abs(f)
+        m.step(10)
+        assert m.objective() >= f - 1e-6 * abs(f)
+        for q in (0, 17):
+            with pytest.raises(nmf.NmfError) as e:
+                m.solve_qn(10, q=q)
+            assert e.value.status == nmf.NMF_EINVAL
