@@ -12,6 +12,7 @@
 // slots 8g..8g+7 (bf16); operand B supplies column j = c at the same slots;
 // result register v of a lane holds D[4g + v][c].
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 
@@ -486,37 +487,42 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  auto compute = [&](const char* buf) {
+  // A stage holds two k-halves (kk) of 16-byte fragments per row.  All
+  // fragment reads of a stage are issued first (two register sets), then
+  // the stage's copies for later, then the MFMAs: the second half's reads
+  // and the copy instructions complete under the first half's MFMAs, so a
+  // wave stalls on LDS once per stage, not once per half.
+  using frag_t = typename std::conditional<BF, v8bf, v4f>::type;
+  frag_t fa[2][MB], fb[2][NB];
+  auto read_frags = [&](const char* buf) {
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      const int q = 4 * kk + g;
-      const int off = 16 * (q ^ (c & 7));
+      const int off = 16 * ((4 * kk + g) ^ (c & 7));
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+        fa[kk][i] = *reinterpret_cast<const frag_t*>(buf + (wm * 16 * MB + 16 * i + c) * 128 + off);
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        fb[kk][j] =
+            *reinterpret_cast<const frag_t*>(buf + (BM + wn * 16 * NB + 16 * j + c) * 128 + off);
+    }
+  };
+  auto mfmas = [&]() {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
       if constexpr (BF) {
-        v8bf a[MB], b[NB];
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-          a[i] = *reinterpret_cast<const v8bf*>(buf + (wm * 16 * MB + 16 * i + c) * 128 + off);
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          b[j] = *reinterpret_cast<const v8bf*>(buf + (BM + wn * 16 * NB + 16 * j + c) * 128 + off);
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < NB; ++j) acc[i][j] = mfma_bf16(fa[kk][i], fb[kk][j], acc[i][j]);
       } else {
-        v4f a[MB], b[NB];
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-          a[i] = *reinterpret_cast<const v4f*>(buf + (wm * 16 * MB + 16 * i + c) * 128 + off);
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          b[j] = *reinterpret_cast<const v4f*>(buf + (BM + wn * 16 * NB + 16 * j + c) * 128 + off);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
           for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j) acc[i][j] = mfma_f32(a[i][t], b[j][t], acc[i][j]);
+            for (int j = 0; j < NB; ++j)
+              acc[i][j] = mfma_f32(fa[kk][i][t], fb[kk][j][t], acc[i][j]);
       }
     }
   };
@@ -524,7 +530,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
   // Stage st lives in buffer st % S.  At the top of iteration st, stages
   // st .. st + S - 2 have been issued; once this wave's copies of stage st
   // have landed, one barrier certifies both that every wave's copies of
-  // stage st are in LDS and that every wave has finished computing stage
+  // stage st are in LDS and that every wave has finished reading stage
   // st - 1, whose buffer is then refilled with stage st + S - 1.
   const int pre = nst < S - 1 ? nst : S - 1;
   for (int st = 0; st < pre; ++st) issue(st);
@@ -537,8 +543,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
     const int later = nst - 1 - st;
     wait_stage<L, S>(later < S - 2 ? later : S - 2);
     lds_barrier();
+    read_frags(lds + (st % S) * STAGE);
     if (st + S - 1 < nst) issue(st + S - 1);
-    compute(lds + (st % S) * STAGE);
+    mfmas();
   }
 
   if (gr.at_end) gram_reduce_slice(gr);
@@ -2007,6 +2014,17 @@ static const DmaEntry kDma[] = {
     // rank 256, BF16: all ranks in one workgroup of 8 waves (two per SIMD)
     DME(4, 4, 4, 2, 3),  // 16: 256 x 128  pass 2, 3 stages (144 KB)
     DME(4, 4, 2, 4, 3),  // 17: 128 x 256  pass 1, 3 stages
+    // 64 x 64 per wave at rank 64 (16 accumulators, 8 fragment reads per
+    // 4 k): two-wave tiles (two workgroups per CU) and four-wave tiles
+    DME(4, 4, 2, 1, 3),  // 18: 128 x 64   pass 1, 72 KB
+    DME(4, 4, 1, 2, 3),  // 19: 64 x 128   pass 2, 72 KB
+    DME(4, 4, 4, 1, 3),  // 20: 256 x 64   pass 1, 120 KB
+    DME(4, 4, 1, 4, 3),  // 21: 64 x 256   pass 2, 120 KB
+    DME(4, 4, 4, 1, 2),  // 22: 256 x 64   pass 1, 80 KB
+    DME(4, 4, 1, 4, 2),  // 23: 64 x 256   pass 2, 80 KB
+    // rank 64, 2 stages (48 KB): three workgroups per CU
+    DME(2, 4, 4, 1, 2),  // 24: 128 x 64   pass 1
+    DME(2, 4, 2, 2, 2),  // 25: 64 x 128   pass 2
 };
 #undef DME
 static const int kDmaCount = sizeof(kDma) / sizeof(kDma[0]);
@@ -2027,6 +2045,10 @@ DmaCfg dma_config(int rp, bool pass1, bool narrow, bool bf16) {
   // us, pass 1 165 -> 160 us against 128 x 128 tiles; in FP32, bound by the
   // matrix cores, the 128 x 128 tiles are as fast)
   if (rp == 256 && bf16) return dma_config_by_id(pass1 ? 17 : 16);
+  // BF16 at rank 128: 256 x 128 / 128 x 256 tiles of 8 waves, 3 stages (with
+  // about 256 workgroups: 8192 x 32768, 126.8 -> 121.5 and 128.5 -> 118.7 us
+  // against 128 x 128 tiles with 2 stages)
+  if (rp == 128 && bf16) return dma_config_by_id(pass1 ? 16 : 17);
   if (rp > 64) return dma_config_by_id(3);
   if (narrow) {
     if (pass1) return dma_config_by_id(rp == 16 ? 13 : rp == 32 ? 11 : 9);

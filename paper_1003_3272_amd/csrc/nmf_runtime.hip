@@ -552,7 +552,10 @@ nmf_status setup(nmf_ctx* c) {
   c->lwt = spread_pitch(ppad, es, pad_vt);
 
   // tiles and splits (environment overrides are tuning knobs)
-  const int64_t target = env_int("NMF_SPLIT_TARGET", 512);
+  // workgroups the split-K plan aims at: 512 (two per CU), 256 for the
+  // one-per-CU BF16 tiles of ranks 128 and 256 (8192 x 32768, rank 256:
+  // 158 -> 153 us per pass)
+  const int64_t target = env_int("NMF_SPLIT_TARGET", (c->bf16 && rp >= 128) ? 256 : 512);
   const int64_t target2 = env_int("NMF_SPLIT_TARGET2", target);
   const int64_t gtarget = env_int("NMF_GRAM_TARGET", 256);
   const int64_t gmin = env_int("NMF_GRAM_MINSTEPS", 8);
