@@ -136,6 +136,11 @@ hipError_t launch_update_h(int rp, int64_t n, int r, const float* part,
 hipError_t launch_objective(int rp, const float* V, int64_t ldv, int64_t p,
                             int64_t n, const float* Wp, const float* Hp,
                             int64_t ldh, double* part, hipStream_t st);
+// The same partials with W H formed on the float64 matrix cores (the same
+// tiles and order of tile sums; the k order inside a dot product differs).
+hipError_t launch_objective_mma(int rp, const float* V, int64_t ldv, int64_t p,
+                                int64_t n, const float* Wp, const float* Hp,
+                                int64_t ldh, double* part, hipStream_t st);
 int64_t objective_parts(int64_t p, int64_t n);
 // out[0] = sum of part[0..count) in a fixed order.
 hipError_t launch_reduce_f64(const double* part, int64_t count, double* out,

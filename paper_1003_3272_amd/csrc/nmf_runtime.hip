@@ -331,6 +331,20 @@ nmf_status iterate(nmf_ctx* c) {
   return half_h(c);
 }
 
+// Euclidean objective partials of (Wp, Hp) into c->fpart: on the float64
+// matrix cores from rank 64 up, on the vector units below (where the
+// products are few and the matrix-core form's staging dominates: 4096 x
+// 16384, rank 16: 116 against 151 us; rank 64: 297 against 265 us; 8192 x
+// 32768, rank 256: 3564 against 2703 us).  NMF_OBJECTIVE_VECTOR=1 or =0
+// forces one form.
+hipError_t euclid_objective(nmf_ctx* c, const float* Wp, const float* Hp, hipStream_t st) {
+  static const int64_t force = env_int("NMF_OBJECTIVE_VECTOR", -1);
+  const bool vec = force >= 0 ? force != 0 : c->rp < 64;
+  return vec ? launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, Hp, c->npad, c->fpart, st)
+             : launch_objective_mma(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, Hp, c->npad, c->fpart,
+                                    st);
+}
+
 // Objective partials and their float64 reduction into out (device memory,
 // or the mapped pinned host buffer: then no copy operation is needed).
 nmf_status objective_async(nmf_ctx* c, const float* Wp, double* out) {
@@ -339,8 +353,7 @@ nmf_status objective_async(nmf_ctx* c, const float* Wp, double* out) {
     TRY_HIP(launch_kl_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart,
                                 c->st));
   else
-    TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, c->Hp, c->npad, c->fpart,
-                             c->st));
+    TRY_HIP(euclid_objective(c, Wp, c->Hp, c->st));
   TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, out, c->st));
   return NMF_OK;
 }
@@ -418,11 +431,9 @@ nmf_status qn_enqueue(nmf_ctx* c) {
   TRY_HIP(launch_qn_dots_solve(c->qU, c->qV, D, q, c->qst, c->qdpart, c->qGUU, c->qGUV, c->qcoef,
                                c->st));
   TRY_HIP(launch_qn_combine(c->qx1, c->qV, c->qcoef, D, q, kQnKappa, c->qst, c->qxq, c->st));
-  TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, c->Wp, c->Hp, c->npad, c->fpart,
-                           c->st));
+  TRY_HIP(euclid_objective(c, c->Wp, c->Hp, c->st));
   TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, c->qf + 0, c->st));
-  TRY_HIP(launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, c->qxq,
-                           c->qxq + c->ppad * c->rp, c->npad, c->fpart, c->st));
+  TRY_HIP(euclid_objective(c, c->qxq, c->qxq + c->ppad * c->rp, c->st));
   TRY_HIP(launch_reduce_f64(c->fpart, c->nparts, c->qf + 1, c->st));
   TRY_HIP(launch_qn_select(c->qf, c->qst, c->qfout_dev, kQnCap, c->st));
   TRY_HIP(launch_qn_commit(c->qst, c->qxq, c->Wp, c->ppad, c->rp, c->npad, c->p, c->r, c->n,
