@@ -474,8 +474,12 @@ nmf_status nmf_pet_step(nmf_pet* m, int32_t iters);
 nmf_status nmf_pet_objective(nmf_pet* m, double* f_host);
 
 /* Iterate until |f_k - f_prev| / (|f_prev| + 1) < tol at a check (every
-   check_every iterations; the stopping rule of Sec. 3) or max_iters.
-   Returns NMF_OK, NMF_ENOTCONVERGED at the cap, NMF_ENONFINITE. */
+   check_every iterations; the stopping rule of Sec. 3) or max_iters.  The
+   rule is tested on the device after every block of check_every iterations
+   (replayed graphs of 8 blocks; the blocks after the one where it holds do
+   nothing), so the result is that of the host loop "step(check_every),
+   objective, test" to the bit.  Synchronizes.  Returns NMF_OK,
+   NMF_ENOTCONVERGED at the cap, NMF_ENONFINITE. */
 nmf_status nmf_pet_solve(nmf_pet* m, int32_t max_iters, double tol, int32_t check_every,
                          int32_t* iters_done_host, double* f_host);
 

@@ -220,7 +220,9 @@ __device__ __forceinline__ float pet_root(float t, const float* __restrict__ lam
 __global__ __launch_bounds__(256) void k_pet_forward(const float* __restrict__ Es, int64_t d,
                                                      int64_t p, const float* __restrict__ lam,
                                                      const float* __restrict__ y,
-                                                     float* __restrict__ ratio) {
+                                                     float* __restrict__ ratio,
+    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // the solve has stopped
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= d) return;
@@ -243,7 +245,9 @@ __global__ __launch_bounds__(256) void k_pet_backward(const float* __restrict__ 
                                                       int64_t p, const float* __restrict__ ratio,
                                                       const float* __restrict__ lam, int rows,
                                                       int cols, float mu,
-                                                      float* __restrict__ out) {
+                                                      float* __restrict__ out,
+    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // the solve has stopped
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j >= p) return;
@@ -268,7 +272,9 @@ __global__ __launch_bounds__(256) void k_pet_forward_ell(const float* __restrict
                                                          int64_t wr, int64_t d,
                                                          const float* __restrict__ lam,
                                                          const float* __restrict__ y,
-                                                         float* __restrict__ ratio) {
+                                                         float* __restrict__ ratio,
+    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // the solve has stopped
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= d) return;
@@ -290,7 +296,9 @@ __global__ __launch_bounds__(256) void k_pet_backward_ell(const float* __restric
                                                           const float* __restrict__ ratio,
                                                           const float* __restrict__ lam, int rows,
                                                           int cols, float mu,
-                                                          float* __restrict__ out) {
+                                                          float* __restrict__ out,
+    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // the solve has stopped
   const int64_t j = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
   const int g = threadIdx.x % G;
   if (j >= p) return;  // whole groups leave together
@@ -303,7 +311,9 @@ __global__ __launch_bounds__(256) void k_pet_backward_ell(const float* __restric
   if (g == 0) out[j] = pet_root(t, lam, j, rows, cols, mu);
 }
 
-__global__ void k_pet_copy(const float* __restrict__ src, float* __restrict__ dst, int64_t p) {
+__global__ void k_pet_copy(const float* __restrict__ src, float* __restrict__ dst, int64_t p,
+    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // the solve has stopped
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < p; j += (int64_t)gridDim.x * 256)
     dst[j] = src[j];
 }
@@ -333,7 +343,9 @@ __global__ __launch_bounds__(256) void k_pet_objective(const float* __restrict__
                                                        int64_t p, const float* __restrict__ lam,
                                                        const float* __restrict__ y, int rows,
                                                        int cols, double mu, double sign,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part,
+    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // the solve has stopped
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w < d) {
@@ -351,7 +363,9 @@ __global__ __launch_bounds__(256) void k_pet_objective(const float* __restrict__
 __global__ __launch_bounds__(256) void k_pet_objective_ell(
     const float* __restrict__ val, const int32_t* __restrict__ idx, const int32_t* __restrict__ cnt,
     int64_t wr, int64_t d, int64_t p, const float* __restrict__ lam, const float* __restrict__ y,
-    int rows, int cols, double mu, double sign, double* __restrict__ part) {
+    int rows, int cols, double mu, double sign, double* __restrict__ part,
+    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // the solve has stopped
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w < d) {
@@ -376,6 +390,40 @@ __global__ void k_pet_qn_commit(const int32_t* __restrict__ st, const float* __r
     lam[j] = xq[j];
 }
 
+// The stopping rule on the device, after a block of check_every iterations
+// and the objective of its result (f in sd[1]): st = {stop, iterations done,
+// iteration cap, check_every}, sd = {f at the previous check, f, tol}.
+// stop: 1 the rule held, 2 another block would pass the cap, 3 f is not
+// finite.  Once stop is set, every gated kernel of later blocks returns at
+// once.
+__global__ void k_pet_test(int32_t* __restrict__ st, double* __restrict__ sd) {
+  if (blockIdx.x != 0 || threadIdx.x != 0 || st[0] != 0) return;
+  const int32_t it = st[1] + st[3];
+  st[1] = it;
+  const double f = sd[1], fp = sd[0];
+  if (!isfinite(f)) {
+    st[0] = 3;
+    return;
+  }
+  sd[0] = f;
+  if (fabs(f - fp) / (fabs(fp) + 1.0) < sd[2])
+    st[0] = 1;
+  else if (it + st[3] > st[2])
+    st[0] = 2;
+}
+
+__global__ void k_pet_solve_init(int32_t* __restrict__ st, double* __restrict__ sd, int32_t cap,
+                                 int32_t check_every, double f0, double tol) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  st[0] = 0;
+  st[1] = 0;
+  st[2] = cap;
+  st[3] = check_every;
+  sd[0] = f0;
+  sd[1] = f0;
+  sd[2] = tol;
+}
+
 unsigned pblocks(int64_t total, int64_t cap = 65535) {
   const int64_t b = (total + 255) / 256;
   return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
@@ -383,6 +431,7 @@ unsigned pblocks(int64_t total, int64_t cap = 65535) {
 
 constexpr int kPetGraphs = 5;  // graphs of 1, 2, 4, 8 and 16 iterations
 constexpr int32_t kPetQnCap = 65536;  // QN iterations recorded per solve
+constexpr int kPetSolveBlocks = 8;    // check blocks per replay of the solve graph
 constexpr float kPetQnKappa = 0.5f;   // projection lambda >= kappa F(lambda)
 
 }  // namespace
@@ -410,6 +459,12 @@ struct nmf_pet {
   double* hostbuf_dev = nullptr;  // the same memory as the device addresses it
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gp[kPetGraphs] = {};
+  // device-side stopping rule of nmf_pet_solve
+  const int32_t* gate = nullptr;  // the stop flag while a solve graph is captured
+  int32_t* sst = nullptr;         // {stop, iterations, cap, check_every}
+  double* ssd = nullptr;          // {f_prev, f, tol}
+  hipGraphExec_t solve_graph = nullptr;
+  int32_t solve_check = 0;  // check_every of solve_graph
   // QN(q)
   int qn_q = 0;
   void* qn_ws = nullptr;
@@ -443,30 +498,31 @@ nmf_status pet_iter(nmf_pet* m, const float* src, float* dst) {
   const unsigned lines = (unsigned)((m->d + 3) / 4);
   if (!m->sparse) {
     hipLaunchKernelGGL(k_pet_forward, dim3(lines), dim3(256), 0, m->st, m->Es, m->d, m->p, src,
-                       m->y, m->ratio);
+                       m->y, m->ratio, m->gate);
     PTRY_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_pet_backward, dim3((unsigned)((m->p + 3) / 4)), dim3(256), 0, m->st,
-                       m->EsT, m->dpad, m->p, m->ratio, src, m->rows, m->cols, m->mu, dst);
+                       m->EsT, m->dpad, m->p, m->ratio, src, m->rows, m->cols, m->mu, dst,
+                       m->gate);
     PTRY_HIP(hipGetLastError());
     return NMF_OK;
   }
   hipLaunchKernelGGL(k_pet_forward_ell, dim3(lines), dim3(256), 0, m->st, m->rval, m->ridx,
-                     m->rowcnt, m->wr, m->d, src, m->y, m->ratio);
+                     m->rowcnt, m->wr, m->d, src, m->y, m->ratio, m->gate);
   PTRY_HIP(hipGetLastError());
   const int g = m->group;
   const unsigned blocks = (unsigned)((m->p + 256 / g - 1) / (256 / g));
   if (g == 16)
     hipLaunchKernelGGL(k_pet_backward_ell<16>, dim3(blocks), dim3(256), 0, m->st, m->cval,
                        m->cidx, m->colcnt, m->wc, m->p, m->ratio, src, m->rows, m->cols, m->mu,
-                       dst);
+                       dst, m->gate);
   else if (g == 32)
     hipLaunchKernelGGL(k_pet_backward_ell<32>, dim3(blocks), dim3(256), 0, m->st, m->cval,
                        m->cidx, m->colcnt, m->wc, m->p, m->ratio, src, m->rows, m->cols, m->mu,
-                       dst);
+                       dst, m->gate);
   else
     hipLaunchKernelGGL(k_pet_backward_ell<64>, dim3(blocks), dim3(256), 0, m->st, m->cval,
                        m->cidx, m->colcnt, m->wc, m->p, m->ratio, src, m->rows, m->cols, m->mu,
-                       dst);
+                       dst, m->gate);
   PTRY_HIP(hipGetLastError());
   return NMF_OK;
 }
@@ -481,7 +537,7 @@ nmf_status pet_iters(nmf_pet* m, int iters) {
   }
   if (iters & 1) {
     hipLaunchKernelGGL(k_pet_copy, dim3(pblocks(m->p, 1024)), dim3(256), 0, m->st, m->lam2,
-                       m->lam, m->p);
+                       m->lam, m->p, m->gate);
     PTRY_HIP(hipGetLastError());
   }
   return NMF_OK;
@@ -515,10 +571,10 @@ nmf_status pet_objective_enqueue(nmf_pet* m, const float* lam, double sign, doub
   if (m->sparse)
     hipLaunchKernelGGL(k_pet_objective_ell, dim3(blocks), dim3(256), 0, m->st, m->rval, m->ridx,
                        m->rowcnt, m->wr, m->d, m->p, lam, m->y, m->rows, m->cols, m->mu_d, sign,
-                       m->part);
+                       m->part, m->gate);
   else
     hipLaunchKernelGGL(k_pet_objective, dim3(blocks), dim3(256), 0, m->st, m->Es, m->d, m->p, lam,
-                       m->y, m->rows, m->cols, m->mu_d, sign, m->part);
+                       m->y, m->rows, m->cols, m->mu_d, sign, m->part, m->gate);
   PTRY_HIP(hipGetLastError());
   PTRY_HIP(launch_reduce_f64(m->part, m->d + m->p, out, m->st));
   return NMF_OK;
@@ -565,6 +621,7 @@ nmf_status pet_qn_prepare(nmf_pet* m, int q) {
   const int qm = qn_max_q();
   if (m->qn_q != q || !m->qn_ws) {
     if (m->qn_graph) (void)hipGraphExecDestroy(m->qn_graph);
+  if (m->solve_graph) (void)hipGraphExecDestroy(m->solve_graph);
     m->qn_graph = nullptr;
     if (m->qn_ws) (void)hipFree(m->qn_ws);
     m->qn_ws = nullptr;
@@ -629,6 +686,44 @@ nmf_status pet_qn_prepare(nmf_pet* m, int q) {
   return NMF_OK;
 }
 
+// kPetSolveBlocks check blocks, each check_every gated iterations, the gated
+// objective into ssd[1] and the test, captured as one graph.
+nmf_status pet_solve_capture(nmf_pet* m, int32_t check_every) {
+  if (m->solve_graph && m->solve_check == check_every) return NMF_OK;
+  if (m->solve_graph) (void)hipGraphExecDestroy(m->solve_graph);
+  m->solve_graph = nullptr;
+  if (!m->cap_stream) PTRY_HIP(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+  PTRY_HIP(hipStreamSynchronize(m->st));
+  hipStream_t user = m->st;
+  m->st = m->cap_stream;
+  m->gate = m->sst;
+  hipGraph_t graph = nullptr;
+  nmf_status s = NMF_OK;
+  if (hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    s = NMF_EDEVICE;
+  if (s == NMF_OK) {
+    for (int b = 0; b < kPetSolveBlocks && s == NMF_OK; ++b) {
+      s = pet_iters(m, check_every);
+      if (s == NMF_OK) s = pet_objective_enqueue(m, m->lam, 1.0, m->ssd + 1);
+      if (s == NMF_OK) {
+        hipLaunchKernelGGL(k_pet_test, dim3(1), dim3(64), 0, m->st, m->sst, m->ssd);
+        if (hipGetLastError() != hipSuccess) s = NMF_EDEVICE;
+      }
+    }
+    const hipError_t e = hipStreamEndCapture(m->cap_stream, &graph);
+    if (s == NMF_OK && (e != hipSuccess || !graph)) s = NMF_EDEVICE;
+  }
+  m->gate = nullptr;
+  m->st = user;
+  if (s == NMF_OK && (hipGraphInstantiate(&m->solve_graph, graph, nullptr, nullptr, 0) !=
+                          hipSuccess ||
+                      hipGraphUpload(m->solve_graph, m->st) != hipSuccess))
+    s = NMF_EDEVICE;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (s == NMF_OK) m->solve_check = check_every;
+  return s;
+}
+
 void pet_free(nmf_pet* m) {
   if (!m) return;
   for (hipGraphExec_t g : m->gp)
@@ -651,6 +746,7 @@ nmf_status pet_setup(nmf_pet* m, const float* E, const float* y, int32_t layout)
   const size_t olam2 = a.take(4 * (size_t)p), ocs = a.take(8 * (size_t)p);
   const size_t opart = a.take(8 * (size_t)(d + p)), orc = a.take(4 * (size_t)d);
   const size_t occ = a.take(4 * (size_t)p), ofl = a.take(4);
+  const size_t osst = a.take(4 * 4), ossd = a.take(8 * 4);
   if (hipMalloc(&m->ws, a.off) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&m->hostbuf), 4 * sizeof(double),
                     hipHostMallocCoherent) != hipSuccess) {
@@ -667,6 +763,8 @@ nmf_status pet_setup(nmf_pet* m, const float* E, const float* y, int32_t layout)
   m->rowcnt = reinterpret_cast<int32_t*>(b + orc);
   m->colcnt = reinterpret_cast<int32_t*>(b + occ);
   m->flag = reinterpret_cast<uint32_t*>(b + ofl);
+  m->sst = reinterpret_cast<int32_t*>(b + osst);
+  m->ssd = reinterpret_cast<double*>(b + ossd);
   // zero everything (the ratios' padding must read as zero)
   PTRY_HIP(launch_fill_u32(static_cast<uint32_t*>(m->ws), (int64_t)(a.off / 4), 0u, m->st));
   // E, y and the start must be finite and nonnegative
@@ -811,6 +909,34 @@ nmf_status nmf_pet_solve(nmf_pet* m, int32_t max_iters, double tol, int32_t chec
   *f_host = f_prev;
   if (s != NMF_OK) return s;
   int32_t k = 0;
+  if (max_iters >= check_every) {
+    // whole check blocks on the device: the rule is tested there after each
+    // block and stops the blocks after it; the host reads the state once per
+    // replay of kPetSolveBlocks blocks
+    s = pet_solve_capture(m, check_every);
+    if (s != NMF_OK) return s;
+    hipLaunchKernelGGL(k_pet_solve_init, dim3(1), dim3(64), 0, m->st, m->sst, m->ssd, max_iters,
+                       check_every, f_prev, tol);
+    PTRY_HIP(hipGetLastError());
+    int32_t* hs = reinterpret_cast<int32_t*>(m->hostbuf);  // pinned
+    const int64_t blocks = max_iters / check_every;
+    for (int64_t r = 0; r <= blocks / kPetSolveBlocks; ++r) {
+      PTRY_HIP(hipGraphLaunch(m->solve_graph, m->st));
+      PTRY_HIP(hipMemcpyAsync(hs, m->sst, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, m->st));
+      PTRY_HIP(hipStreamSynchronize(m->st));
+      if (hs[0] != 0) break;
+    }
+    const int32_t stop = hs[0];
+    k = hs[1];
+    PTRY_HIP(hipMemcpyAsync(m->hostbuf, m->ssd, 2 * sizeof(double), hipMemcpyDeviceToHost, m->st));
+    PTRY_HIP(hipStreamSynchronize(m->st));
+    *iters_done = k;
+    *f_host = m->hostbuf[1];
+    f_prev = m->hostbuf[0];
+    if (stop == 1) return NMF_OK;
+    if (stop == 3) return NMF_ENONFINITE;
+    // stop == 2: fewer than check_every iterations remain
+  }
   while (k < max_iters) {
     const int32_t todo = std::min(check_every, max_iters - k);
     s = nmf_pet_step(m, todo);

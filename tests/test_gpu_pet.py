@@ -269,3 +269,32 @@ def test_pet_qn_then_plain_steps_continue(gpu_lib):
             with pytest.raises(nmf.NmfError) as e:
                 m.solve_qn(10, q=q)
             assert e.value.status == nmf.NMF_EINVAL
+
+
+@pytest.mark.parametrize("check_every,max_iters", [(3, 500), (1, 40), (7, 45)])
+def test_pet_solve_matches_a_host_loop(gpu_lib, full_problem, check_every, max_iters):
+    """The solve tests the rule on the device between replayed blocks of
+    iterations; a host loop of steps and objectives with the same rule must
+    stop at the same iteration with the same f and intensities, bit for bit
+    (including a last block shorter than check_every at the cap)."""
+    from paper_1003_3272_amd import nmf
+    E, y, rows, cols = full_problem
+    Ed, yd = torch.from_numpy(E).cuda(), torch.from_numpy(y).cuda()
+    la = torch.ones(E.shape[1], dtype=torch.float32, device="cuda")
+    lb = torch.ones(E.shape[1], dtype=torch.float32, device="cuda")
+    tol = 1e-7 if max_iters == 500 else 0.0
+    with nmf.Pet(Ed, yd, la, rows, cols, 1e-3) as ma, nmf.Pet(Ed, yd, lb, rows, cols, 1e-3) as mb:
+        conv, it, f = ma.solve(max_iters, tol=tol, check_every=check_every)
+        f_prev, k, conv_b = mb.objective(), 0, False
+        while k < max_iters:
+            todo = min(check_every, max_iters - k)
+            mb.step(todo)
+            k += todo
+            fb = mb.objective()
+            if abs(fb - f_prev) / (abs(f_prev) + 1.0) < tol:
+                conv_b = True
+                break
+            f_prev = fb
+        assert (conv, it) == (conv_b, k)
+        assert f == fb
+    assert torch.equal(la, lb)
