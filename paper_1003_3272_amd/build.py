@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmf.so")
-SOURCES = ["nmf_kernels.hip", "nmf_objective.hip", "nmf_kl.hip", "nmf_qn.hip",
+SOURCES = ["nmf_kernels.hip", "nmf_objective.hip", "nmf_update.hip", "nmf_kl.hip", "nmf_qn.hip",
            "nmf_runtime.hip", "nmf_mlp.hip", "nmf_batch.hip", "nmf_pet.hip"]
 ARCH = "gfx950"
 

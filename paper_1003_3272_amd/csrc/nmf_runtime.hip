@@ -271,6 +271,9 @@ nmf_status half_w(nmf_ctx* c) {
   return c->fuse ? NMF_OK : gram_w(c);
 }
 
+hipError_t update_h_call(nmf_ctx* c, const float* part, int64_t ldp, int64_t sp, int splits,
+                         const float* G, uint16_t* Hb, float* gout, bool gram_only);
+
 nmf_status half_h(nmf_ctx* c) {
   const GramRed gr =
       c->fuse ? GramRed{c->gpw, c->uw_grid, c->rp * c->rp, c->GW, c->gram_at_end} : kNoGram;
@@ -283,9 +286,8 @@ nmf_status half_h(nmf_ctx* c) {
   }
   {
     StageTimer t(c, NMF_STAGE_UPDATE_H);
-    TRY_HIP(launch_update_h(c->rp, c->n, c->r, c->part2, c->s2.ldp, c->s2.sp, c->s2.splits,
-                            c->GW, c->Hp, c->npad, c->Huser, c->bf16 ? c->Hb : nullptr, c->bf16,
-                            c->fuse ? c->gph : nullptr, c->uh_grid, c->uh_cols, false, c->st));
+    TRY_HIP(update_h_call(c, c->part2, c->s2.ldp, c->s2.sp, c->s2.splits, c->GW,
+                          c->bf16 ? c->Hb : nullptr, c->fuse ? c->gph : nullptr, false));
   }
   return c->fuse ? NMF_OK : gram_h(c);
 }
@@ -329,6 +331,20 @@ nmf_status iterate(nmf_ctx* c) {
   if (c->kl) return kl_iter(c);
   TRY(half_w(c));
   return half_h(c);
+}
+
+// The H update (or, gram_only, the Gram partials of the current H): up to
+// rank 64 with its small products on the matrix cores (NMF_UPDATE_H_VALU=1:
+// the vector-unit kernel, whose sums run in another order).
+hipError_t update_h_call(nmf_ctx* c, const float* part, int64_t ldp, int64_t sp, int splits,
+                         const float* G, uint16_t* Hb, float* gout, bool gram_only) {
+  static const bool valu = env_int("NMF_UPDATE_H_VALU", 0) != 0;
+  if (c->rp <= 64 && !valu)
+    return launch_update_h_mf(c->rp, c->n, c->r, part, ldp, sp, splits, G, c->Hp, c->npad,
+                              c->Huser, Hb, c->bf16, gout, c->uh_grid, c->uh_cols, gram_only,
+                              c->st);
+  return launch_update_h(c->rp, c->n, c->r, part, ldp, sp, splits, G, c->Hp, c->npad, c->Huser,
+                         Hb, c->bf16, gout, c->uh_grid, c->uh_cols, gram_only, c->st);
 }
 
 // Euclidean objective partials of (Wp, Hp) into c->fpart: on the float64
@@ -443,9 +459,7 @@ nmf_status qn_enqueue(nmf_ctx* c) {
     TRY_HIP(launch_update_w(c->rp, c->p, c->r, nullptr, 0, 0, 0, nullptr, c->Wp, c->Wuser,
                             nullptr, nullptr, 0, c->bf16, c->gpw, c->uw_grid, c->uw_kpt, true,
                             c->st));
-    TRY_HIP(launch_update_h(c->rp, c->n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, c->npad,
-                            c->Huser, nullptr, c->bf16, c->gph, c->uh_grid, c->uh_cols, true,
-                            c->st));
+    TRY_HIP(update_h_call(c, nullptr, 0, 0, 0, nullptr, nullptr, c->gph, true));
   } else {
     TRY(gram_h(c));
     TRY(gram_w(c));
@@ -744,8 +758,7 @@ nmf_status setup(nmf_ctx* c) {
     // per-workgroup Grams of the start; the first products reduce them
     TRY_HIP(launch_update_w(rp, p, c->r, nullptr, 0, 0, 0, nullptr, c->Wp, c->Wuser, nullptr,
                             nullptr, 0, c->bf16, c->gpw, c->uw_grid, c->uw_kpt, true, c->st));
-    TRY_HIP(launch_update_h(rp, n, c->r, nullptr, 0, 0, 0, nullptr, c->Hp, npad, c->Huser,
-                            nullptr, c->bf16, c->gph, c->uh_grid, c->uh_cols, true, c->st));
+    TRY_HIP(update_h_call(c, nullptr, 0, 0, 0, nullptr, nullptr, c->gph, true));
   } else if (!c->kl) {
     TRY(gram_h(c));
     TRY(gram_w(c));
