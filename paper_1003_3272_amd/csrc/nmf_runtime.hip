@@ -355,7 +355,9 @@ hipError_t update_h_call(nmf_ctx* c, const float* part, int64_t ldp, int64_t sp,
 // forces one form.
 hipError_t euclid_objective(nmf_ctx* c, const float* Wp, const float* Hp, hipStream_t st) {
   static const int64_t force = env_int("NMF_OBJECTIVE_VECTOR", -1);
-  const bool vec = force >= 0 ? force != 0 : c->rp < 64;
+  // W = 0 (||V||^2, once per context) is a plain streaming sum: the vector
+  // kernel's float4 loads do it in half the time
+  const bool vec = force >= 0 ? force != 0 : (c->rp < 64 || Wp == nullptr);
   return vec ? launch_objective(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, Hp, c->npad, c->fpart, st)
              : launch_objective_mma(c->rp, c->Vk, c->ldvk, c->p, c->n, Wp, Hp, c->npad, c->fpart,
                                     st);
