@@ -16,6 +16,10 @@ window of the same number of iterations, launched directly) and the FP64
 CPU oracle timed on a bounded sample of the same workload, on one host core
 and on all of them.
 
+Unless --no-ceilings, the rates this GPU sustains (nmf_ceiling: an HBM read
+stream and the matrix-core and vector instructions the kernels use) are
+measured after the headline's windows, and every pass roofline also states
+the time bound they give and the fraction of it the pass reaches.
 Then (unless --no-stream-reference) a plain 1.07 GB device copy by torch, as
 a practical HBM streaming rate beside the 8000 GB/s peak.
 Then (unless --no-rank-sweep) the same shape at ranks 8, 16, 32 and 64 in
@@ -48,6 +52,7 @@ METRIC = "NMF iters/sec + time to 1e-4 rel. objective gap: FP32 vs BF16+warm-sta
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+PEAK_F64_TFLOPS = 78.6
 
 
 def parse():
@@ -62,6 +67,8 @@ def parse():
     ap.add_argument("--ldv-pad", type=int, default=0,
                     help="extra floats per V row in device memory (row-stride experiment)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-tier run")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the measured rate ceilings (nmf_ceiling)")
     ap.add_argument("--no-stream-reference", action="store_true",
                     help="skip the reference copy that measures a practical HBM rate")
     ap.add_argument("--no-precision-tier", action="store_true",
@@ -257,6 +264,55 @@ def profiled_steps(ctx, steps):
     return ctx.profile_stop()
 
 
+# rates measured on this GPU by nmf_ceiling (None until measured_ceilings runs)
+CEILINGS = None
+
+
+def measured_ceilings():
+    """What this GPU sustains, beside the published peaks: an HBM read stream
+    over a 1 GiB buffer (best of 10 passes in one timed window) and the dense
+    throughput of the matrix-core and vector instructions the kernels use.
+    Measured after the headline's timed windows, outside any of them."""
+    import torch
+
+    from paper_1003_3272_amd import nmf
+    global CEILINGS
+    buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    rate = {k: nmf.ceiling(k, buf, reps=10 if k == "hbm_read" else 5) for k in nmf.CEILING_KINDS}
+    del buf
+    torch.cuda.empty_cache()
+    CEILINGS = {
+        "hbm_read_GBps": round(rate["hbm_read"] / 1e9, 1),
+        "mfma_fp32_TFLOPs": round(rate["mfma_f32"] / 1e12, 1),
+        "mfma_bf16_TFLOPs": round(rate["mfma_bf16"] / 1e12, 1),
+        "mfma_f64_TFLOPs": round(rate["mfma_f64"] / 1e12, 1),
+        "fma_f64_TFLOPs": round(rate["fma_f64"] / 1e12, 1),
+        "fraction_of_published": {
+            "hbm_read": round(rate["hbm_read"] / 1e9 / PEAK_HBM_GBS, 3),
+            "mfma_fp32": round(rate["mfma_f32"] / 1e12 / PEAK_TFLOPS["fp32"], 3),
+            "mfma_bf16": round(rate["mfma_bf16"] / 1e12 / PEAK_TFLOPS["bf16"], 3),
+            "mfma_f64": round(rate["mfma_f64"] / 1e12 / PEAK_F64_TFLOPS, 3),
+            "fma_f64": round(rate["fma_f64"] / 1e12 / PEAK_F64_TFLOPS, 3)},
+        "how": "nmf_ceiling: a read-only stream of 1020 MiB, and 2048 workgroups of 4 waves "
+               "issuing independent chains of one instruction (v_mfma_f32_16x16x4f32, "
+               "v_mfma_f32_16x16x32_bf16, v_mfma_f64_16x16x4f64, v_fma_f64) with no memory "
+               "traffic; each rate timed with HIP events over 5-10 launches"}
+    return CEILINGS
+
+
+def _measured_bound(roof, flops, vbytes, prec, ms):
+    """The pass's time bound from the measured ceilings (the slower of its
+    flops at the measured matrix-core rate and its V bytes at the measured
+    read rate), and the fraction of it the pass reaches."""
+    if CEILINGS is None:
+        return
+    t_mma = flops / (CEILINGS[f"mfma_{prec}_TFLOPs"] * 1e12)
+    t_hbm = vbytes / (CEILINGS["hbm_read_GBps"] * 1e9)
+    roof["measured_bound"] = "mfma" if t_mma >= t_hbm else "hbm"
+    roof["measured_bound_ms"] = round(1e3 * max(t_mma, t_hbm), 4)
+    roof["frac_of_measured_bound"] = round(max(t_mma, t_hbm) / (ms * 1e-3), 4)
+
+
 def pass_roofline(stages, p, n, r, prec):
     """Roofline of the slower V-streaming pass: 2 p n r flops and p n s_V
     bytes of V per launch (s_V = 4 for FP32, 2 for BF16), against whichever
@@ -278,6 +334,7 @@ def pass_roofline(stages, p, n, r, prec):
     roof["kernel_ms"] = round(ms, 4)
     roof["v_pass_gbs"] = round(vbytes / (ms * 1e-3) / 1e9, 1)
     roof["other_pass_ms"] = round(passes["gemm_wtv" if dom == "gemm_vht" else "gemm_vht"], 4)
+    _measured_bound(roof, flops, vbytes, prec, ms)
     return roof
 
 
@@ -344,6 +401,7 @@ def poisson_experiment(Vd, args, log):
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS["fp32"], 4), "kernel": dom,
                 "kernel_ms": round(ms, 4), "v_pass_gbs": round(4.0 * p * n / (ms * 1e-3) / 1e9, 1),
                 "flops_per_pass": "4 p n r (B = W H recomputed, then the numerator)"}
+        _measured_bound(roof, flops, 4.0 * p * n, "fp32", ms)
         out["ranks"][str(r)] = {
             "iters_per_s": round(args.sweep_steps / el, 1), "roofline": roof,
             "stages_ms_per_iter": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()
@@ -780,6 +838,8 @@ def main():
 
     iters_per_s = args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
+    if not args.no_ceilings:
+        measured_ceilings()
     roof = pass_roofline(stages, p, n, r, args.precision)
     roof["traffic"] = measured_traffic(roof["kernel"], p, n, r, args.precision)
     roof["timing"] = ("kernel_ms: mean HIP-event duration of the launches of that pass in a "
@@ -821,6 +881,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_stream_reference:
         out["hbm_reference"] = stream_reference()
+    if CEILINGS is not None:
+        out["measured_ceilings"] = CEILINGS
     if not args.no_pet:
         out["pet"] = pet_experiment(args, log)
         torch.cuda.empty_cache()

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmf.so")
 SOURCES = ["nmf_kernels.hip", "nmf_objective.hip", "nmf_update.hip", "nmf_kl.hip", "nmf_qn.hip",
-           "nmf_runtime.hip", "nmf_mlp.hip", "nmf_batch.hip", "nmf_pet.hip"]
+           "nmf_runtime.hip", "nmf_mlp.hip", "nmf_batch.hip", "nmf_pet.hip", "nmf_ceiling.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for device code; hipcc's host pass

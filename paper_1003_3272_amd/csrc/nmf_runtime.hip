@@ -579,10 +579,12 @@ nmf_status setup(nmf_ctx* c) {
   c->lwt = spread_pitch(ppad, es, pad_vt);
 
   // tiles and splits (environment overrides are tuning knobs)
-  // workgroups the split-K plan aims at: 512 (two per CU), 256 for the
-  // one-per-CU BF16 tiles of ranks 128 and 256 (8192 x 32768, rank 256:
-  // 158 -> 153 us per pass)
-  const int64_t target = env_int("NMF_SPLIT_TARGET", (c->bf16 && rp >= 128) ? 256 : 512);
+  // workgroups the split-K plan aims at: 512 (two per CU) in FP32, 256 in
+  // BF16, whose passes stream half the bytes and gain more from half the
+  // partials than from the second workgroup per CU (8192 x 32768, rank 256:
+  // 158 -> 153 us per pass; 4096 x 16384, ranks 32 and 64: 64.0 -> 61.6 and
+  // 90.3 -> 85.6 us per iteration; 8192 x 32768 ranks 32 and 64 unchanged)
+  const int64_t target = env_int("NMF_SPLIT_TARGET", c->bf16 ? 256 : 512);
   const int64_t target2 = env_int("NMF_SPLIT_TARGET2", target);
   const int64_t gtarget = env_int("NMF_GRAM_TARGET", 256);
   const int64_t gmin = env_int("NMF_GRAM_MINSTEPS", 8);

@@ -170,6 +170,8 @@ def load(path: str = LIB_PATH):
     lib.nmf_pet_solve_qn.restype = c_int32
     lib.nmf_pet_destroy.argtypes = [P]
     lib.nmf_pet_destroy.restype = None
+    lib.nmf_ceiling.argtypes = [c_int32, P, c_int64, c_int32, POINTER(c_double), P]
+    lib.nmf_ceiling.restype = c_int32
     lib.nmf_strerror.argtypes = [c_int32]
     lib.nmf_strerror.restype = ctypes.c_char_p
     lib.nmf_version.argtypes = []
@@ -214,6 +216,22 @@ def normalize_gauge_noalloc(W, H, stream=None):
                                             _stream_handle(stream))
     if st != NMF_OK:
         raise NmfError(st, "nmf_normalize_gauge_noalloc")
+
+
+CEILING_KINDS = {"hbm_read": 0, "mfma_f32": 1, "mfma_bf16": 2, "mfma_f64": 3, "fma_f64": 4}
+
+
+def ceiling(kind, buf, reps=10, stream=None):
+    """Measured rate of the current device for one kind of CEILING_KINDS
+    (bytes/s for hbm_read, flop/s otherwise); buf is a CUDA tensor of at
+    least 64 MiB whose contents are overwritten."""
+    rate = c_double(0.0)
+    st = load().nmf_ceiling(CEILING_KINDS[kind] if isinstance(kind, str) else int(kind),
+                            c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                            int(reps), byref(rate), _stream_handle(stream))
+    if st != NMF_OK:
+        raise NmfError(st, "nmf_ceiling")
+    return rate.value
 
 
 def _stream_handle(stream):

@@ -231,3 +231,18 @@ def test_pet_calls_reject_bad_arguments_before_device_work():
     assert lib.nmf_pet_solve(None, 10, 1e-9, 1, ctypes.byref(it), ctypes.byref(f)) == \
         nmf.NMF_EINVAL
     lib.nmf_pet_destroy(None)
+
+
+def test_ceiling_rejects_bad_arguments_before_device_work():
+    lib = nmf.load()
+    rate = ctypes.c_double(-1.0)
+    R = ctypes.byref(rate)
+    big = 64 << 20
+    cases = [(-1, FAKE, big, 5, R), (5, FAKE, big, 5, R),          # unknown kind
+             (0, None, big, 5, R), (1, FAKE, big, 5, None),        # null pointers
+             (1, FAKE, big - 256, 5, R), (1, FAKE, big + 8, 5, R),  # too small, not 256-aligned
+             (2, FAKE, big, 0, R), (2, FAKE, big, 1001, R),        # reps out of range
+             (3, FAKE + 16, big, 5, R)]                           # buffer not 256-aligned
+    for args in cases:
+        assert lib.nmf_ceiling(*args, None) == nmf.NMF_EINVAL, args
+    assert rate.value == -1.0
