@@ -23,7 +23,9 @@ typedef enum {
   NMF_CEIL_MFMA_F32 = 1,   /* flop/s of v_mfma_f32_16x16x4f32                */
   NMF_CEIL_MFMA_BF16 = 2,  /* flop/s of v_mfma_f32_16x16x32_bf16             */
   NMF_CEIL_MFMA_F64 = 3,   /* flop/s of v_mfma_f64_16x16x4f64                */
-  NMF_CEIL_FMA_F64 = 4     /* flop/s of the float64 vector FMA               */
+  NMF_CEIL_FMA_F64 = 4,    /* flop/s of the float64 vector FMA               */
+  NMF_CEIL_MFMA_F32_32 = 5,  /* flop/s of v_mfma_f32_32x32x2f32              */
+  NMF_CEIL_MFMA_BF16_32 = 6  /* flop/s of v_mfma_f32_32x32x16_bf16           */
 } nmf_ceiling_kind;
 
 /* Measures one rate of the current device: one untimed launch, then reps

@@ -12,6 +12,7 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kGrid = 2048;                    // workgroups of the compute kinds
@@ -92,6 +93,39 @@ __global__ __launch_bounds__(kThreads) void k_mfma_bf16(double* __restrict__ sin
   sink[(int64_t)blockIdx.x * kThreads + threadIdx.x] = s;
 }
 
+// the 32 x 32 shapes: v_mfma_f32_32x32x2f32 (BF false) or
+// v_mfma_f32_32x32x16_bf16 (BF true)
+template <int CH, bool BF>
+__global__ __launch_bounds__(kThreads) void k_mfma32(double* __restrict__ sink, int iters,
+                                                    float a0) {
+  v16f acc[CH];
+#pragma unroll
+  for (int i = 0; i < CH; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[i][e] = 0.f;
+  const float af = a0 + threadIdx.x * 1e-7f, bfv = a0 * 0.5f;
+  v8bf a, b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    a[e] = (__bf16)(a0 + threadIdx.x * 1e-3f);
+    b[e] = (__bf16)(a0 * 0.5f);
+  }
+  for (int it = 0; it < iters; ++it)
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      if constexpr (BF)
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
+      else
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(af, bfv, acc[i], 0, 0, 0);
+    }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < CH; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) s += acc[i][e];
+  sink[(int64_t)blockIdx.x * kThreads + threadIdx.x] = s;
+}
+
 template <int CH>
 __global__ __launch_bounds__(kThreads) void k_fma_f64(double* __restrict__ sink, int iters,
                                                      double a0) {
@@ -139,6 +173,14 @@ hipError_t launch_kind(int32_t kind, void* buf, int64_t bytes, hipStream_t st, d
       hipLaunchKernelGGL(k_fma_f64<16>, g, b, 0, st, sink, 4096, 1.0);
       *work = (double)kGrid * kThreads * 4096 * 16 * 2.0;
       break;
+    case NMF_CEIL_MFMA_F32_32:
+      hipLaunchKernelGGL((k_mfma32<4, false>), g, b, 0, st, sink, 1024, 1.f);
+      *work = waves * 1024 * 4 * 2.0 * 32 * 32 * 2;
+      break;
+    case NMF_CEIL_MFMA_BF16_32:
+      hipLaunchKernelGGL((k_mfma32<4, true>), g, b, 0, st, sink, 512, 1.f);
+      *work = waves * 512 * 4 * 2.0 * 32 * 32 * 16;
+      break;
     default:
       return hipErrorInvalidValue;
   }
@@ -149,7 +191,7 @@ hipError_t launch_kind(int32_t kind, void* buf, int64_t bytes, hipStream_t st, d
 
 extern "C" int32_t nmf_ceiling(int32_t kind, void* buf, int64_t bytes, int32_t reps,
                                double* rate_host, void* stream) {
-  if (kind < NMF_CEIL_HBM_READ || kind > NMF_CEIL_FMA_F64 || !buf || !rate_host ||
+  if (kind < NMF_CEIL_HBM_READ || kind > NMF_CEIL_MFMA_BF16_32 || !buf || !rate_host ||
       bytes < kMinBytes || bytes % 256 != 0 || reps < 1 || reps > 1000)
     return -1;
   if (reinterpret_cast<uintptr_t>(buf) % 256 != 0) return -1;

@@ -22,6 +22,8 @@
 namespace nmfk {
 namespace {
 
+typedef float v16f __attribute__((ext_vector_type(16)));  // a 32 x 32 MFMA accumulator
+
 // 4 consecutive floats of row `row`, columns col..col+3, zero outside
 // [0, rows) x [0, cols).  The vector path needs ld % 4 == 0 and a 16-byte
 // aligned base, which every caller guarantees.
@@ -431,17 +433,26 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(
 // latency is covered by S - 1 stages of MFMA work.  Inside a row, 16-byte
 // chunk q is stored at slot q ^ (row % 8): the 16 lanes of an MFMA fragment
 // (rows c = 0..15, same chunk) then hit distinct LDS banks.
-// FP32: a chunk is 4 k-values, fed to 4 v_mfma_f32_16x16x4_f32 (slot g of
-// MFMA t is k = 16 kk + 4 g + t).  BF16: a chunk is the 8 k-values a lane
-// supplies to one v_mfma_f32_16x16x32_bf16.
+// SH = 16, FP32: a chunk is 4 k-values, fed to 4 v_mfma_f32_16x16x4_f32
+// (slot g of MFMA t is k = 16 kk + 4 g + t).  BF16: a chunk is the 8
+// k-values a lane supplies to one v_mfma_f32_16x16x32_bf16.
+// SH = 32 (the 32 x 32 matrix-core shapes, which sustain more flops on this
+// chip: v_mfma_f32_32x32x2f32 and v_mfma_f32_32x32x16_bf16): a wave owns
+// (32 MB) x (32 NB) outputs; lane (c, h) = (lane % 32, lane / 32) reads
+// chunk 2 j + h of row c for k-group j of the stage, so in FP32 slot h of
+// MFMA t of group j is k = 8 j + 4 h + t, and in BF16 the lane supplies the
+// chunk's 8 k to one MFMA.  The accumulator of a 32 x 32 block holds
+// D[8 (v / 4) + 4 h + v % 4][c] in element v (an in-bounds layout probe on
+// the GPU confirmed it for both shapes).  MB and NB count 16- or 32-blocks.
 // ---------------------------------------------------------------------------
-template <int MB, int NB, int WM, int WN, int S, bool BF>
+template <int MB, int NB, int WM, int WN, int S, bool BF, int SH>
 __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
     const void* __restrict__ Xv, int64_t ldx, const void* __restrict__ Yv, int64_t ldy,
     int64_t K, int64_t kchunk, float* __restrict__ part, int64_t ldp, int64_t sp, GramRed gr) {
+  static_assert(SH == 16 || SH == 32, "MFMA shape");
   constexpr int ES = BF ? 2 : 4;
   constexpr int BKE = 128 / ES;
-  constexpr int BM = 16 * MB * WM, BN = 16 * NB * WN, ROWS = BM + BN;
+  constexpr int BM = SH * MB * WM, BN = SH * NB * WN, ROWS = BM + BN;
   constexpr int W = WM * WN;
   static_assert(ROWS % (8 * W) == 0, "stage rows must split evenly over the waves");
   constexpr int L = ROWS / (8 * W);  // DMA instructions per wave per stage
@@ -481,48 +492,66 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
                                        (lds_ptr_t)(dst + (wave * L + j) * 1024), 16, 0, 0);
   };
 
-  v4f acc[MB][NB];
+  // accumulator of one SH x SH block
+  using acc_t = typename std::conditional<SH == 32, v16f, v4f>::type;
+  constexpr int AE = SH * SH / 64;  // accumulator elements per lane and block
+  acc_t acc[MB][NB];
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int e = 0; e < AE; ++e) acc[i][j][e] = 0.f;
 
-  // A stage holds two k-halves (kk) of 16-byte fragments per row.  All
-  // fragment reads of a stage are issued first (two register sets), then
-  // the stage's copies for later, then the MFMAs: the second half's reads
-  // and the copy instructions complete under the first half's MFMAs, so a
-  // wave stalls on LDS once per stage, not once per half.
+  // A stage holds KG k-groups of 16-byte fragments per row (SH = 16: two
+  // halves kk, lane group g reading chunk 4 kk + g; SH = 32: four groups j,
+  // lane half h reading chunk 2 j + h).  All fragment reads of a stage are
+  // issued first, then the stage's copies for later, then the MFMAs: the
+  // later groups' reads and the copy instructions complete under the first
+  // group's MFMAs, so a wave stalls on LDS once per stage, not per group.
   using frag_t = typename std::conditional<BF, v8bf, v4f>::type;
-  frag_t fa[2][MB], fb[2][NB];
+  constexpr int KG = SH == 32 ? 4 : 2;
+  const int fr = SH == 32 ? (lane & 31) : c;            // fragment row of this lane
+  const int fq = SH == 32 ? (lane >> 5) : g;            // chunk within a k-group
+  frag_t fa[KG][MB], fb[KG][NB];
   auto read_frags = [&](const char* buf) {
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const int off = 16 * ((4 * kk + g) ^ (c & 7));
+    for (int kk = 0; kk < KG; ++kk) {
+      const int off = 16 * (((8 / KG) * kk + fq) ^ (fr & 7));
 #pragma unroll
       for (int i = 0; i < MB; ++i)
-        fa[kk][i] = *reinterpret_cast<const frag_t*>(buf + (wm * 16 * MB + 16 * i + c) * 128 + off);
+        fa[kk][i] = *reinterpret_cast<const frag_t*>(buf + (wm * SH * MB + SH * i + fr) * 128 + off);
 #pragma unroll
       for (int j = 0; j < NB; ++j)
         fb[kk][j] =
-            *reinterpret_cast<const frag_t*>(buf + (BM + wn * 16 * NB + 16 * j + c) * 128 + off);
+            *reinterpret_cast<const frag_t*>(buf + (BM + wn * SH * NB + SH * j + fr) * 128 + off);
     }
   };
   auto mfmas = [&]() {
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
+    for (int kk = 0; kk < KG; ++kk) {
       if constexpr (BF) {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j) acc[i][j] = mfma_bf16(fa[kk][i], fb[kk][j], acc[i][j]);
+          for (int j = 0; j < NB; ++j) {
+            if constexpr (SH == 32)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[kk][i], fb[kk][j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = mfma_bf16(fa[kk][i], fb[kk][j], acc[i][j]);
+          }
       } else {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
           for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
-              acc[i][j] = mfma_f32(fa[kk][i][t], fb[kk][j][t], acc[i][j]);
+            for (int j = 0; j < NB; ++j) {
+              if constexpr (SH == 32)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[kk][i][t], fb[kk][j][t], acc[i][j], 0, 0, 0);
+              else
+                acc[i][j] = mfma_f32(fa[kk][i][t], fb[kk][j][t], acc[i][j]);
+            }
       }
     }
   };
@@ -555,9 +584,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_nt_dma(
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wm * 16 * MB + 16 * i + 4 * g + v;
-        const int64_t col = n0 + wn * 16 * NB + 16 * j + c;
+      for (int v = 0; v < AE; ++v) {
+        const int rr = SH == 32 ? 8 * (v / 4) + 4 * fq + (v % 4) : 4 * g + v;
+        const int64_t row = m0 + wm * SH * MB + SH * i + rr;
+        const int64_t col = n0 + wn * SH * NB + SH * j + fr;
         P[row * ldp + col] = acc[i][j][v];
       }
 }
@@ -1975,22 +2005,27 @@ hipError_t launch_gemm_nt_bf16(const NtCfg& cfg, const uint16_t* X, int64_t ldx,
 typedef hipError_t (*DmaLaunch)(const void*, int64_t, const void*, int64_t, int64_t, int64_t,
                                 float*, int64_t, int64_t, const GramRed&, dim3, hipStream_t);
 
-template <int MB, int NB, int WM, int WN, int S, bool BF>
+template <int MB, int NB, int WM, int WN, int S, bool BF, int SH>
 hipError_t dma_inst(const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t K,
                     int64_t kchunk, float* part, int64_t ldp, int64_t sp, const GramRed& gr,
                     dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_nt_dma<MB, NB, WM, WN, S, BF>), grid, dim3(64 * WM * WN), 0, st, X, ldx,
-                     Y, ldy, K, kchunk, part, ldp, sp, gr);
+  hipLaunchKernelGGL((k_nt_dma<MB, NB, WM, WN, S, BF, SH>), grid, dim3(64 * WM * WN), 0, st, X,
+                     ldx, Y, ldy, K, kchunk, part, ldp, sp, gr);
   return hipGetLastError();
 }
 
 struct DmaEntry {
-  int mb, nb, wm, wn, s;
+  int sh, mb, nb, wm, wn, s;
   DmaLaunch f32, bf16;
 };
-#define DME(MB, NB, WM, WN, S) \
-  {MB, NB, WM, WN, S, &dma_inst<MB, NB, WM, WN, S, false>, &dma_inst<MB, NB, WM, WN, S, true>}
-// id: (MB, NB, WM, WN, stages); tile (16 MB WM) x (16 NB WN)
+#define DME(MB, NB, WM, WN, S)                                              \
+  {16, MB, NB, WM, WN, S, &dma_inst<MB, NB, WM, WN, S, false, 16>,          \
+   &dma_inst<MB, NB, WM, WN, S, true, 16>}
+#define DME32(MB, NB, WM, WN, S)                                            \
+  {32, MB, NB, WM, WN, S, &dma_inst<MB, NB, WM, WN, S, false, 32>,          \
+   &dma_inst<MB, NB, WM, WN, S, true, 32>}
+// id: (MB, NB, WM, WN, stages); tile (SH MB WM) x (SH NB WN), SH = 16 for
+// DME and 32 for DME32
 static const DmaEntry kDma[] = {
     DME(4, 1, 2, 1, 3),  // 0: 128 x 16   pass 1, r <= 16
     DME(2, 2, 4, 1, 3),  // 1: 128 x 32   pass 1, r <= 32
@@ -2025,16 +2060,29 @@ static const DmaEntry kDma[] = {
     // rank 64, 2 stages (48 KB): three workgroups per CU
     DME(2, 4, 4, 1, 2),  // 24: 128 x 64   pass 1
     DME(2, 4, 2, 2, 2),  // 25: 64 x 128   pass 2
+    // the same tiles on the 32 x 32 matrix-core shapes
+    DME32(1, 2, 4, 1, 3),  // 26: 128 x 64   pass 1, r <= 64 (as 2)
+    DME32(1, 2, 2, 2, 3),  // 27: 64 x 128   pass 2, r <= 64 (as 6)
+    DME32(1, 1, 4, 1, 3),  // 28: 128 x 32   pass 1, r <= 32 (as 1)
+    DME32(1, 1, 1, 4, 3),  // 29: 32 x 128   pass 2, r <= 32 (as 5)
+    DME32(2, 2, 2, 2, 2),  // 30: 128 x 128  r > 64 (as 3)
+    DME32(2, 2, 4, 2, 3),  // 31: 256 x 128  pass 2, 8 waves (as 16)
+    DME32(2, 2, 2, 4, 3),  // 32: 128 x 256  pass 1, 8 waves (as 17)
+    DME32(1, 1, 2, 2, 3),  // 33: 64 x 64    pass 1, r <= 64 narrow (as 9)
+    DME32(1, 1, 2, 2, 3),  // 34: 64 x 64    pass 2, r <= 64 narrow (as 10)
+    DME32(1, 1, 2, 1, 3),  // 35: 64 x 32    pass 1, r <= 32 narrow (as 11)
+    DME32(1, 1, 1, 2, 3),  // 36: 32 x 64    pass 2, r <= 32 narrow (as 12)
 };
 #undef DME
+#undef DME32
 static const int kDmaCount = sizeof(kDma) / sizeof(kDma[0]);
 
 DmaCfg dma_config_by_id(int id) {
   if (id < 0 || id >= kDmaCount) id = 2;
   DmaCfg c;
   c.id = id;
-  c.bm = 16 * kDma[id].mb * kDma[id].wm;
-  c.bn = 16 * kDma[id].nb * kDma[id].wn;
+  c.bm = kDma[id].sh * kDma[id].mb * kDma[id].wm;
+  c.bn = kDma[id].sh * kDma[id].nb * kDma[id].wn;
   c.threads = 64 * kDma[id].wm * kDma[id].wn;
   return c;
 }
@@ -2049,11 +2097,16 @@ DmaCfg dma_config(int rp, bool pass1, bool narrow, bool bf16) {
   // about 256 workgroups: 8192 x 32768, 126.8 -> 121.5 and 128.5 -> 118.7 us
   // against 128 x 128 tiles with 2 stages)
   if (rp == 128 && bf16) return dma_config_by_id(pass1 ? 16 : 17);
-  if (rp > 64) return dma_config_by_id(3);
+  // FP32 from rank 64 up: the 32 x 32 matrix-core shape (8192 x 32768, rank
+  // 128: 553.8 -> 512.9 us per pass; 4096 x 16384, rank 64: 179.8 -> 177.2
+  // us per iteration); at lower ranks, on the narrow tiles and in BF16 the
+  // 16 x 16 shapes measured as fast or faster
+  if (rp > 64) return dma_config_by_id(bf16 ? 3 : 30);
   if (narrow) {
     if (pass1) return dma_config_by_id(rp == 16 ? 13 : rp == 32 ? 11 : 9);
     return dma_config_by_id(rp == 16 ? 14 : rp == 32 ? 12 : 10);
   }
+  if (rp == 64 && !bf16) return dma_config_by_id(pass1 ? 26 : 27);
   if (pass1) return dma_config_by_id(rp == 16 ? 0 : rp == 32 ? 1 : 2);
   return dma_config_by_id(rp == 16 ? 4 : rp == 32 ? 5 : 6);
 }

@@ -218,7 +218,8 @@ def normalize_gauge_noalloc(W, H, stream=None):
         raise NmfError(st, "nmf_normalize_gauge_noalloc")
 
 
-CEILING_KINDS = {"hbm_read": 0, "mfma_f32": 1, "mfma_bf16": 2, "mfma_f64": 3, "fma_f64": 4}
+CEILING_KINDS = {"hbm_read": 0, "mfma_f32": 1, "mfma_bf16": 2, "mfma_f64": 3, "fma_f64": 4,
+                 "mfma_f32_32": 5, "mfma_bf16_32": 6}
 
 
 def ceiling(kind, buf, reps=10, stream=None):

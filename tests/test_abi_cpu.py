@@ -238,7 +238,7 @@ def test_ceiling_rejects_bad_arguments_before_device_work():
     rate = ctypes.c_double(-1.0)
     R = ctypes.byref(rate)
     big = 64 << 20
-    cases = [(-1, FAKE, big, 5, R), (5, FAKE, big, 5, R),          # unknown kind
+    cases = [(-1, FAKE, big, 5, R), (7, FAKE, big, 5, R),          # unknown kind
              (0, None, big, 5, R), (1, FAKE, big, 5, None),        # null pointers
              (1, FAKE, big - 256, 5, R), (1, FAKE, big + 8, 5, R),  # too small, not 256-aligned
              (2, FAKE, big, 0, R), (2, FAKE, big, 1001, R),        # reps out of range

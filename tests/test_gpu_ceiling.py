@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 # published peaks: HBM bytes/s; dense flop/s of each instruction's type
 PEAK = {"hbm_read": 8.0e12, "mfma_f32": 157.3e12, "mfma_bf16": 2.5e15, "mfma_f64": 78.6e12,
-        "fma_f64": 78.6e12}
+        "fma_f64": 78.6e12, "mfma_f32_32": 157.3e12, "mfma_bf16_32": 2.5e15}
 
 
 @pytest.fixture(scope="module")
