@@ -59,7 +59,7 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--p", type=int, default=4096)
     ap.add_argument("--n", type=int, default=16384)
@@ -99,6 +99,9 @@ def parse():
                     help="training targets: each training matrix solved to this gap (the "
                          "solver-converged factors); <= 0 uses --ws-target-iters iterations")
     ap.add_argument("--ws-target-iters", type=int, default=200)
+    ap.add_argument("--ws-dict-iters", type=int, default=3000,
+                    help="iterations of the joint factorization that gives W-bar")
+    ap.add_argument("--ws-dict-precision", choices=["fp32", "bf16"], default="bf16")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="budget of each FP64 oracle baseline leg (0 disables)")
     ap.add_argument("--cpu-gap-seconds", type=float, default=60.0,
@@ -717,7 +720,8 @@ def warm_start_experiment(args, log):
     del mats
     train, test = Vs[:args.ws_train], Vs[args.ws_train:]
     t0 = time.perf_counter()
-    Wbar = ws.mean_dictionary(train[:16], 48, iters=600, precision="bf16")
+    Wbar = ws.mean_dictionary(train[:16], 48, iters=args.ws_dict_iters,
+                              precision=args.ws_dict_precision)
     t_dict = time.perf_counter() - t0
     t0 = time.perf_counter()
     Hs = []
