@@ -75,6 +75,8 @@ def test_half_steps_elementwise(gpu_lib):
 # -------------------------------------------------- ragged shapes, all ranks
 SHAPES = [
     (1000, 3001, 64),   # several tiles + ragged tails on both sides
+    (2000, 8000, 64),   # enough tiles for the default (not the narrow) rank-64
+    (2000, 8000, 40),   # tiles, 32 x 32 matrix-core shape, ragged tails
     (77, 130, 3),       # smaller than one tile
     (513, 257, 17),     # rank padded 17 -> 32
     (300, 1000, 100),   # rank padded to 128
