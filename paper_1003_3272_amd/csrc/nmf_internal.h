@@ -45,6 +45,7 @@ struct GramRed {
   int elems;
   float* G;
   int at_end;  // V-streaming products: reduce after the main loop, not before
+  int wide;    // chunks of 32 elements per workgroup (large Grams), else one element per 32 lanes
 };
 
 NtCfg nt_config(int rp, bool gram);

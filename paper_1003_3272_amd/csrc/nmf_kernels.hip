@@ -62,17 +62,55 @@ __device__ __forceinline__ uint4 load8h(const uint16_t* __restrict__ p,
 // ---------------------------------------------------------------------------
 // Distributed Gram reduction carried by a product kernel: G[e] = sum_q
 // part[q][e] over the `count` per-workgroup Gram partials written by the
-// previous update kernel.  Workgroups take elements round-robin; 32 lanes
-// share an element, each summing partials q = lane, lane + 32, ... in order,
-// then a fixed xor butterfly combines the 32 lane sums (commutative at each
-// level, so every lane holds the same bits).  The result does not depend on
-// the product's grid.
+// previous update kernel, in one of two fixed orders (chosen by the host
+// per padded rank, so every kernel that carries a given Gram gives the same
+// bits; neither depends on the product's grid or workgroup size):
+//  - wide: workgroups take chunks of 32 consecutive elements round-robin,
+//    so every load instruction of a wave reads whole 128-byte lines.  The
+//    partial range is cut into kGramSlots fixed slots; slot k of element e
+//    is summed by one thread in ascending q (32 loads in flight), and the
+//    slot sums are added in slot order through LDS;
+//  - otherwise (small Grams, too few chunks to spread): workgroups take
+//    elements round-robin; 32 lanes share an element, each summing partials
+//    q = lane, lane + 32, ... in order, then a fixed xor butterfly combines
+//    the 32 lane sums (commutative at each level, so every lane holds the
+//    same bits).
 // ---------------------------------------------------------------------------
+constexpr int kGramSlots = 8;
 __device__ __forceinline__ void gram_reduce_slice(const GramRed& g) {
   if (!g.part) return;
+  __shared__ float slot_sum[kGramSlots][32];
   const int64_t nwg = (int64_t)gridDim.x * gridDim.y * gridDim.z;
   const int64_t b = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
-  const int groups = blockDim.x >> 5, grp = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+  const int groups = (int)(blockDim.x >> 5), grp = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+  if (g.wide) {
+    const int per = (g.count + kGramSlots - 1) / kGramSlots;
+    for (int64_t e0 = b * 32; e0 < g.elems; e0 += nwg * 32) {
+      const int64_t e = e0 + l32;
+      for (int k = grp; k < kGramSlots; k += groups) {
+        const int q0 = k * per, q1 = q0 + per < g.count ? q0 + per : g.count;
+        float s = 0.f;
+        for (int q = q0; q < q1; q += 32) {
+          float v[32];
+#pragma unroll
+          for (int u = 0; u < 32; ++u)
+            v[u] = (e < g.elems && q + u < q1) ? g.part[(int64_t)(q + u) * g.elems + e] : 0.f;
+#pragma unroll
+          for (int u = 0; u < 32; ++u) s += v[u];
+        }
+        slot_sum[k][l32] = s;
+      }
+      lds_barrier();
+      if (grp == 0 && e < g.elems) {
+        float t = slot_sum[0][l32];
+#pragma unroll
+        for (int k = 1; k < kGramSlots; ++k) t += slot_sum[k][l32];
+        g.G[e] = t;
+      }
+      lds_barrier();  // slot_sum is reused by the next chunk
+    }
+    return;
+  }
   for (int64_t e0 = b * groups; e0 < g.elems; e0 += nwg * groups) {
     const int64_t e = e0 + grp;
     float s = 0.f;

@@ -138,6 +138,7 @@ struct nmf_ctx {
   float* kl_den = nullptr;  // Poisson: 2 x rp denominators (row sums of H, column sums of W)
   bool fuse = false;      // rp <= 64: Grams formed in the update kernels
   int gram_at_end = 0;    // the products reduce the Gram partials after their loop
+  int gram_wide = 0;      // ... in chunks of 32 elements per workgroup
   int uw_grid = 1, uh_grid = 1;
   int uw_kpt = 4, uh_cols = 64;  // block shapes of the update kernels
   DmaCfg d1{}, d2{};      // the two V-streaming products
@@ -208,7 +209,7 @@ void profile_release(nmf_ctx* c) {
   c->prof_used = 0;
 }
 
-const GramRed kNoGram = {nullptr, 0, 0, nullptr, 0};
+const GramRed kNoGram = {nullptr, 0, 0, nullptr, 0, 0};
 
 nmf_status check_ptr(const void* p) {
   if (!p) return NMF_EINVAL;
@@ -252,7 +253,8 @@ nmf_status gram_w(nmf_ctx* c) {
 nmf_status half_w(nmf_ctx* c) {
   // G_H: reduced inside the product from the H update's per-workgroup Grams
   const GramRed gr =
-      c->fuse ? GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH, c->gram_at_end} : kNoGram;
+      c->fuse ? GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH, c->gram_at_end, c->gram_wide}
+              : kNoGram;
   {
     StageTimer t(c, NMF_STAGE_GEMM_VHT);
     const void* X = c->bf16 ? static_cast<const void*>(c->Vb) : static_cast<const void*>(c->Vk);
@@ -276,7 +278,8 @@ hipError_t update_h_call(nmf_ctx* c, const float* part, int64_t ldp, int64_t sp,
 
 nmf_status half_h(nmf_ctx* c) {
   const GramRed gr =
-      c->fuse ? GramRed{c->gpw, c->uw_grid, c->rp * c->rp, c->GW, c->gram_at_end} : kNoGram;
+      c->fuse ? GramRed{c->gpw, c->uw_grid, c->rp * c->rp, c->GW, c->gram_at_end, c->gram_wide}
+              : kNoGram;
   {
     StageTimer t(c, NMF_STAGE_GEMM_WTV);
     const void* X = c->bf16 ? static_cast<const void*>(c->WbT) : static_cast<const void*>(c->WT);
@@ -625,6 +628,10 @@ nmf_status setup(nmf_ctx* c) {
   // loop (4096 x 16384, rank 64, FP32: 82.5 -> 80.7 us per pass against
   // before it); NMF_GRAM_AT_END=0 restores the reduction before the loop
   c->gram_at_end = env_int("NMF_GRAM_AT_END", 1) == 0 ? 0 : 1;
+  // coalesced chunks of 32 elements for the rank-64 Gram (4096 elements:
+  // 128 chunks); the smaller Grams have too few chunks to spread over the
+  // workgroups and keep one element per 32 lanes (NMF_GRAM_WIDE overrides)
+  c->gram_wide = (int)env_int("NMF_GRAM_WIDE", rp >= 64 ? 1 : 0) != 0;
   if (!c->fuse && !c->kl) {
     if (!c->bf16) {
       c->cgh = nt_config(rp, true);
@@ -1020,7 +1027,7 @@ nmf_status nmf_refit_w(nmf_ctx* c, float floor_rel) {
   if (!c || !(floor_rel > 0.f && floor_rel < 1.f)) return NMF_EINVAL;
   if (c->kl || !c->fuse || c->rp > 64) return NMF_EUNSUPPORTED;
   // A = V H^T as in the W half-step; the same launch reduces G_H
-  const GramRed gr = GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH};
+  const GramRed gr = GramRed{c->gph, c->uh_grid, c->rp * c->rp, c->GH, 0, c->gram_wide};
   const void* X = c->bf16 ? static_cast<const void*>(c->Vb) : static_cast<const void*>(c->Vk);
   const void* Y = c->bf16 ? static_cast<const void*>(c->Hb) : static_cast<const void*>(c->Hp);
   TRY_HIP(launch_nt_dma(c->d1, c->bf16, X, c->bf16 ? c->lvb : c->ldvk, c->p, Y, c->npad, c->rp,
