@@ -624,14 +624,17 @@ nmf_status setup(nmf_ctx* c) {
     c->s2 = plan_split(rp, n, ppad, bm2, bn2, 256, target2, 1);
   }
   c->fuse = rp <= 64 && !c->kl;
-  // the products reduce the previous update's Gram partials after their own
-  // loop (4096 x 16384, rank 64, FP32: 82.5 -> 80.7 us per pass against
-  // before it); NMF_GRAM_AT_END=0 restores the reduction before the loop
-  c->gram_at_end = env_int("NMF_GRAM_AT_END", 1) == 0 ? 0 : 1;
   // coalesced chunks of 32 elements for the rank-64 Gram (4096 elements:
   // 128 chunks); the smaller Grams have too few chunks to spread over the
   // workgroups and keep one element per 32 lanes (NMF_GRAM_WIDE overrides)
   c->gram_wide = (int)env_int("NMF_GRAM_WIDE", rp >= 64 ? 1 : 0) != 0;
+  // where the products reduce the previous update's Gram partials: the
+  // coalesced form before their ring loop, under the first copies
+  // (4096 x 16384, rank 64: 177.5 -> 175.4 us per iteration; BF16 2048 x
+  // 8192: 40.0 -> 38.7 us), the per-element form after it (rank 16: 17.4
+  // against 17.6 us; before the coalesced form, at rank 64 too: 83.7 ->
+  // 80.7 us per pass); NMF_GRAM_AT_END overrides
+  c->gram_at_end = (int)env_int("NMF_GRAM_AT_END", c->gram_wide ? 0 : 1) != 0;
   if (!c->fuse && !c->kl) {
     if (!c->bf16) {
       c->cgh = nt_config(rp, true);
