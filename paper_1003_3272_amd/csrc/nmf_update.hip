@@ -82,6 +82,8 @@ __global__ __launch_bounds__(256) void k_update_h_mf(
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const bool gram = gout != nullptr;
+  // the caller's H takes float4 stores when its rows keep 16-byte alignment
+  const bool hc4 = (n % 4 == 0) && (reinterpret_cast<uintptr_t>(Hc) % 16 == 0);
 
   // G once per workgroup (none for gram_only)
   for (int idx = tid; idx < (gram_only ? 0 : RP * RP / 4); idx += 256) {
@@ -181,12 +183,20 @@ __global__ __launch_bounds__(256) void k_update_h_mf(
           hn.w = (d.w > 0.f) ? h.w * (sm.w / d.w) : h.w;
           const int64_t j = j0 + j4;
           *reinterpret_cast<float4*>(&Hp[(int64_t)kk * ldh + j]) = hn;
-          const float hv[4] = {hn.x, hn.y, hn.z, hn.w};
+          // the bf16 copy has the padded pitch too (its padded columns get
+          // the zeros the padded H holds); the caller's H has pitch n
+          if (Hb)
+            *reinterpret_cast<uint2*>(&Hb[(int64_t)kk * ldh + j]) =
+                make_uint2((uint32_t)to_bf16(hn.x) | ((uint32_t)to_bf16(hn.y) << 16),
+                           (uint32_t)to_bf16(hn.z) | ((uint32_t)to_bf16(hn.w) << 16));
+          if (kk < r) {
+            if (hc4 && j + 3 < n) {
+              *reinterpret_cast<float4*>(&Hc[(int64_t)kk * n + j]) = hn;
+            } else {
+              const float hv[4] = {hn.x, hn.y, hn.z, hn.w};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (j + u < n) {
-              if (kk < r) Hc[(int64_t)kk * n + j + u] = hv[u];
-              if (Hb) Hb[(int64_t)kk * ldh + j + u] = to_bf16(hv[u]);
+              for (int u = 0; u < 4; ++u)
+                if (j + u < n) Hc[(int64_t)kk * n + j + u] = hv[u];
             }
           }
         }
