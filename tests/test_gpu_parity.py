@@ -77,6 +77,7 @@ SHAPES = [
     (1000, 3001, 64),   # several tiles + ragged tails on both sides
     (2000, 8000, 64),   # enough tiles for the default (not the narrow) rank-64
     (2000, 8000, 40),   # tiles, 32 x 32 matrix-core shape, ragged tails
+    (4099, 1000, 64),   # W update with 4 ranks per thread, p % 4 != 0
     (77, 130, 3),       # smaller than one tile
     (513, 257, 17),     # rank padded 17 -> 32
     (300, 1000, 100),   # rank padded to 128
