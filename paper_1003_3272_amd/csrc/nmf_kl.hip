@@ -160,7 +160,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_kl_pass(
 
 // Denominators of both updates from the current factors, float64 sums in a
 // fixed order: den[k] = sum_j H[k][j] (j < n), den[rp + k] = sum_i W[i][k]
-// (i < p).  Grid (rp, 2).
+// (i < p).  Grid (rp, 2).  Thread t sums a contiguous segment of the row
+// (column) in ascending order with 16 loads in flight (float4 items of H,
+// single floats of the strided W column), then the 256 segment sums meet in
+// a fixed tree.
 __global__ __launch_bounds__(256) void k_kl_sums(const float* __restrict__ Wp, int rp, int64_t p,
                                                  const float* __restrict__ Hp, int64_t ldh,
                                                  int64_t n, float* __restrict__ den) {
@@ -168,9 +171,42 @@ __global__ __launch_bounds__(256) void k_kl_sums(const float* __restrict__ Wp, i
   const int k = blockIdx.x, tid = threadIdx.x;
   double s = 0.0;
   if (blockIdx.y == 0) {
-    for (int64_t j = tid; j < n; j += 256) s += (double)Hp[(int64_t)k * ldh + j];
+    // segments of a multiple of 4 columns (rows of H start 16-byte aligned)
+    const int64_t seg = 4 * (((n + 255) / 256 + 3) / 4);
+    const int64_t j0 = tid * seg, j1 = j0 + seg < n ? j0 + seg : n;
+    const float* row = Hp + (int64_t)k * ldh;
+    for (int64_t j = j0; j < j1; j += 64) {
+      float4 v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int64_t jj = j + 4 * u;
+        if (jj + 3 < j1) {
+          v[u] = *reinterpret_cast<const float4*>(row + jj);
+        } else {
+          v[u].x = jj < j1 ? row[jj] : 0.f;
+          v[u].y = jj + 1 < j1 ? row[jj + 1] : 0.f;
+          v[u].z = jj + 2 < j1 ? row[jj + 2] : 0.f;
+          v[u].w = 0.f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        s += (double)v[u].x;
+        s += (double)v[u].y;
+        s += (double)v[u].z;
+        s += (double)v[u].w;
+      }
+    }
   } else {
-    for (int64_t i = tid; i < p; i += 256) s += (double)Wp[i * rp + k];
+    const int64_t seg = (p + 255) / 256;
+    const int64_t i0 = tid * seg, i1 = i0 + seg < p ? i0 + seg : p;
+    for (int64_t i = i0; i < i1; i += 16) {
+      float v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = i + u < i1 ? Wp[(i + u) * rp + k] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += (double)v[u];
+    }
   }
   sh[tid] = s;
   __syncthreads();
