@@ -134,11 +134,14 @@ hipError_t launch_update_h(int rp, int64_t n, int r, const float* part,
                            bool gram_only, hipStream_t st);
 
 // launch_update_h for rp <= 64 with the denominator G H and the Gram
-// partials on the matrix cores (gram_only: the Gram partials of H alone).
+// partials on the matrix cores (gram_only: the Gram partials of H alone;
+// early_g: G is loaded together with the first block's other loads, for
+// grids of at most one workgroup per CU, where the registers that costs do
+// not cut the workgroups that run at once).
 hipError_t launch_update_h_mf(int rp, int64_t n, int r, const float* part, int64_t ldp,
                               int64_t sp, int splits, const float* G, float* Hp, int64_t ldh,
                               float* Hcaller, uint16_t* Hb, bool bf16, float* gout, int grid,
-                              int cols, bool gram_only, hipStream_t st);
+                              int cols, bool gram_only, bool early_g, hipStream_t st);
 
 // Objective partials: one double per 64 x 64 tile of V - W H.
 hipError_t launch_objective(int rp, const float* V, int64_t ldv, int64_t p,

@@ -93,6 +93,7 @@ Split plan_split(int64_t M, int64_t N, int64_t K, int bm, int bn, int bk, int64_
 
 struct nmf_ctx {
   int device = 0;
+  int cus = 0;  // compute units of the device
   hipStream_t st = nullptr;
   int64_t p = 0, n = 0, ldv = 0;
   int r = 0, rp = 0;
@@ -345,7 +346,7 @@ hipError_t update_h_call(nmf_ctx* c, const float* part, int64_t ldp, int64_t sp,
   if (c->rp <= 64 && !valu)
     return launch_update_h_mf(c->rp, c->n, c->r, part, ldp, sp, splits, G, c->Hp, c->npad,
                               c->Huser, Hb, c->bf16, gout, c->uh_grid, c->uh_cols, gram_only,
-                              c->st);
+                              c->uh_grid <= c->cus, c->st);
   return launch_update_h(c->rp, c->n, c->r, part, ldp, sp, splits, G, c->Hp, c->npad, c->Huser,
                          Hb, c->bf16, gout, c->uh_grid, c->uh_cols, gram_only, c->st);
 }
@@ -830,7 +831,9 @@ nmf_status nmf_init(nmf_ctx** out, const float* V, int64_t p, int64_t n, int64_t
   c->Vuser = V;
   c->Wuser = W;
   c->Huser = H;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+          hipSuccess) {
     (void)hipGetLastError();
     free_ctx(c);
     return NMF_EDEVICE;

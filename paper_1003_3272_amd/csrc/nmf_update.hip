@@ -65,7 +65,7 @@ __device__ __forceinline__ void split_sums(const float* __restrict__ part,
 // D[16 mt + 4 g + v][16 w + c].  Gram: wave w owns the 16-rank row tile w
 // (of RP / 16) and every column tile, over K = the block's columns, in the
 // same way.
-template <int RP, int COLS>
+template <int RP, int COLS, bool EG>
 __global__ __launch_bounds__(256) void k_update_h_mf(
     int64_t n, int r, const float* __restrict__ part, int64_t ldp, int64_t sp, int splits,
     const float* __restrict__ G, float* __restrict__ Hp, int64_t ldh, float* __restrict__ Hc,
@@ -85,15 +85,31 @@ __global__ __launch_bounds__(256) void k_update_h_mf(
   // the caller's H takes float4 stores when its rows keep 16-byte alignment
   const bool hc4 = (n % 4 == 0) && (reinterpret_cast<uintptr_t>(Hc) % 16 == 0);
 
-  // G once per workgroup (none for gram_only)
-  for (int idx = tid; idx < (gram_only ? 0 : RP * RP / 4); idx += 256) {
-    const int k = (4 * idx) / RP, l = (4 * idx) % RP;
-    float4 v = *reinterpret_cast<const float4*>(&G[4 * idx]);
-    if (bf16) {
-      v.x = bf16_val(v.x); v.y = bf16_val(v.y); v.z = bf16_val(v.z); v.w = bf16_val(v.w);
+  // G once per workgroup (none for gram_only).  EG: loaded into registers
+  // here and stored to LDS after the first block's own loads have been
+  // issued, so that all of them share one memory round trip (the registers
+  // this holds cost occupancy, so the host picks EG only when the grid is
+  // one workgroup per CU); else staged first, each store waiting for its load.
+  constexpr int NG = EG ? (RP * RP / 4 + 255) / 256 : 1;
+  float4 gq[NG];
+  if constexpr (EG) {
+#pragma unroll
+    for (int e = 0; e < NG; ++e) {
+      const int idx = tid + 256 * e;
+      gq[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!gram_only && idx < RP * RP / 4) gq[e] = *reinterpret_cast<const float4*>(&G[4 * idx]);
     }
-    *reinterpret_cast<float4*>(&Gs[k * GP + l]) = v;
+  } else {
+    for (int idx = tid; idx < (gram_only ? 0 : RP * RP / 4); idx += 256) {
+      const int k = (4 * idx) / RP, l = (4 * idx) % RP;
+      float4 v = *reinterpret_cast<const float4*>(&G[4 * idx]);
+      if (bf16) {
+        v.x = bf16_val(v.x); v.y = bf16_val(v.y); v.z = bf16_val(v.z); v.w = bf16_val(v.w);
+      }
+      *reinterpret_cast<float4*>(&Gs[k * GP + l]) = v;
+    }
   }
+  bool g_staged = !EG || gram_only != 0;
 
   v4f gacc[MT];
 #pragma unroll
@@ -120,6 +136,20 @@ __global__ __launch_bounds__(256) void k_update_h_mf(
     } else {
 #pragma unroll
       for (int e = 0; e < NI; ++e) sv[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (EG && !g_staged) {  // first block only; read after the barriers below
+#pragma unroll
+      for (int e = 0; e < NG; ++e) {
+        const int idx = tid + 256 * e;
+        if (idx >= RP * RP / 4) continue;
+        const int k = (4 * idx) / RP, l = (4 * idx) % RP;
+        float4 v = gq[e];
+        if (bf16) {
+          v.x = bf16_val(v.x); v.y = bf16_val(v.y); v.z = bf16_val(v.z); v.w = bf16_val(v.w);
+        }
+        *reinterpret_cast<float4*>(&Gs[k * GP + l]) = v;
+      }
+      g_staged = true;
     }
     __syncthreads();  // the previous block's Hs / Ds reads are done
 #pragma unroll
@@ -240,10 +270,18 @@ __global__ __launch_bounds__(256) void k_update_h_mf(
 hipError_t launch_update_h_mf(int rp, int64_t n, int r, const float* part, int64_t ldp,
                               int64_t sp, int splits, const float* G, float* Hp, int64_t ldh,
                               float* Hcaller, uint16_t* Hb, bool bf16, float* gout, int grid,
-                              int cols, bool gram_only, hipStream_t st) {
-#define UHF(R, C)                                                                              \
-  hipLaunchKernelGGL((k_update_h_mf<R, C>), dim3(grid), dim3(256), 0, st, n, r, part, ldp, sp, \
-                     splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout, (int)gram_only)
+                              int cols, bool gram_only, bool early_g, hipStream_t st) {
+#define UHF(R, C)                                                                          \
+  do {                                                                                     \
+    if (early_g)                                                                           \
+      hipLaunchKernelGGL((k_update_h_mf<R, C, true>), dim3(grid), dim3(256), 0, st, n, r, part, \
+                         ldp, sp, splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout,         \
+                         (int)gram_only);                                                  \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_update_h_mf<R, C, false>), dim3(grid), dim3(256), 0, st, n, r,   \
+                         part, ldp, sp, splits, G, Hp, ldh, Hcaller, Hb, (int)bf16, gout,   \
+                         (int)gram_only);                                                  \
+  } while (0)
 #define UHC(R)                     \
   do {                             \
     if (cols == 64) UHF(R, 64);    \
