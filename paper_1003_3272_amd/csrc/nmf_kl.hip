@@ -217,6 +217,22 @@ __global__ __launch_bounds__(256) void k_kl_sums(const float* __restrict__ Wp, i
   if (tid == 0) den[blockIdx.y * rp + k] = (float)sh[0];
 }
 
+// sum_s x[s sp] for s < splits, added in ascending s; the loads of 8 splits
+// are issued before they are added, so the sum costs one memory round trip
+// per 8 splits
+__device__ __forceinline__ float split_sum(const float* __restrict__ x, int64_t sp, int splits) {
+  float num = 0.f;
+  for (int s0 = 0; s0 < splits; s0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = s0 + u < splits ? x[(int64_t)(s0 + u) * sp] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s0 + u < splits) num += v[u];
+  }
+  return num;
+}
+
 // w_ik <- w_ik sqrt(num_ik / den_k) for i < p, k < rp, with num = the split
 // sums of pass 1 (in ascending split order) and den = den[k]; den_k <= 0
 // keeps w_ik (padded ranks have den_k = 0 and stay zero, padded rows are not
@@ -230,8 +246,7 @@ __global__ __launch_bounds__(256) void k_kl_update_w(
        idx += (int64_t)gridDim.x * 256) {
     const int64_t i = idx / rp;
     const int k = (int)(idx % rp);
-    float num = 0.f;
-    for (int s = 0; s < splits; ++s) num += part[s * sp + i * ldp + k];
+    const float num = split_sum(part + i * ldp + k, sp, splits);
     const float dk = den[k];
     float w = Wp[idx];
     if (dk > 0.f) w = w * sqrtf(num / dk);
@@ -252,8 +267,7 @@ __global__ __launch_bounds__(256) void k_kl_update_h(
        idx += (int64_t)gridDim.x * 256) {
     const int k = (int)(idx / n);
     const int64_t j = idx % n;
-    float num = 0.f;
-    for (int s = 0; s < splits; ++s) num += part[s * sp + (int64_t)k * ldp + j];
+    const float num = split_sum(part + (int64_t)k * ldp + j, sp, splits);
     const float dk = den[rp + k];
     float h = Hp[(int64_t)k * ldh + j];
     if (dk > 0.f) h = h * sqrtf(num / dk);
