@@ -1357,6 +1357,18 @@ __global__ __launch_bounds__(256 * WR) void k_update_w_mma(
 #pragma unroll
           for (int v = 0; v < 4; ++v) na[i][j][v] += x[i][j][v];
     }
+    // every W value of this lane first (its own entries), so the loads share
+    // one memory round trip instead of waiting one by one behind the stores
+    float wo[MI][NJ][4];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = i0 + ib + 16 * i + 4 * g + v;
+          wo[i][j][v] = row < p ? Wp[row * RP + kb + 16 * j + c] : 0.f;
+        }
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -1370,7 +1382,7 @@ __global__ __launch_bounds__(256 * WR) void k_update_w_mma(
           if (row >= p) continue;
           const float a = na[i][j][v];
           const float b = acc[i][j][v];
-          const float w = Wp[row * RP + k];
+          const float w = wo[i][j][v];
           const float wn = (b > 0.f) ? w * (a / b) : w;
           Wp[row * RP + k] = wn;
           if (k < r) Wc[row * r + k] = wn;
@@ -1438,36 +1450,43 @@ __global__ __launch_bounds__(256 * WC) void k_update_h_mma(
       __syncthreads();
       mma_chunk<MI, NJ, BF>(As, kb, Bs, jb0, acc);
     }
-    // numerators summed over the splits in ascending order, all of this
-    // lane's entries of one split loaded together
-    float ns[MI][NJ][4];
+    // per 16-rank tile i of this lane: the numerators summed over the splits
+    // in ascending order (the tile's entries of one split loaded together),
+    // then its H values, then the updates.  A tile at a time keeps the live
+    // registers few (all tiles at once spilled at rank 256), and a lane's
+    // H values are loaded before its stores (its own entries only) so they
+    // do not wait one by one behind them.
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
+    for (int i = 0; i < MI; ++i) {
+      float ns[NJ][4];
 #pragma unroll
       for (int jb = 0; jb < NJ; ++jb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ns[i][jb][v] = 0.f;
-    for (int q = 0; q < splits; ++q) {
-      float x[MI][NJ][4];
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
+        for (int v = 0; v < 4; ++v) ns[jb][v] = 0.f;
+      for (int q = 0; q < splits; ++q) {
+        float x[NJ][4];
 #pragma unroll
         for (int jb = 0; jb < NJ; ++jb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int64_t j = j0 + jb0 + 16 * jb + c;
-            x[i][jb][v] = 0.f;
-            if (j < n) x[i][jb][v] = part[q * sp + (int64_t)(kb + 16 * i + 4 * g + v) * ldp + j];
+            x[jb][v] = 0.f;
+            if (j < n) x[jb][v] = part[q * sp + (int64_t)(kb + 16 * i + 4 * g + v) * ldp + j];
           }
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int jb = 0; jb < NJ; ++jb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) ns[i][jb][v] += x[i][jb][v];
-    }
+          for (int v = 0; v < 4; ++v) ns[jb][v] += x[jb][v];
+      }
+      float hv[NJ][4];
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
+      for (int jb = 0; jb < NJ; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t j = j0 + jb0 + 16 * jb + c;
+          hv[jb][v] = 0.f;
+          if (j < n) hv[jb][v] = Hp[(int64_t)(kb + 16 * i + 4 * g + v) * ldh + j];
+        }
 #pragma unroll
       for (int jb = 0; jb < NJ; ++jb) {
         const int64_t j = j0 + jb0 + 16 * jb + c;
@@ -1475,15 +1494,16 @@ __global__ __launch_bounds__(256 * WC) void k_update_h_mma(
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = kb + 16 * i + 4 * g + v;
-          const float s = ns[i][jb][v];
+          const float s = ns[jb][v];
           const float d = acc[i][jb][v];
-          const float h = Hp[(int64_t)k * ldh + j];
+          const float h = hv[jb][v];
           const float hn = (d > 0.f) ? h * (s / d) : h;
           Hp[(int64_t)k * ldh + j] = hn;
           if (k < r) Hc[(int64_t)k * n + j] = hn;
           if (Hb) Hb[(int64_t)k * ldh + j] = to_bf16(hn);
         }
       }
+    }
   }
 }
 
