@@ -527,14 +527,25 @@ __device__ __attribute__((noinline)) void tile_h(const Prob& P, int t) {
   // ---- epilogue: D^T = H_cols^T G_W, H <- H * (S / D), partial Gram ------
   float* Hs = lds;                       // [RP][PV]
   float* Gs = lds + 64 * (kMaxNB + 16);  // [RP][PR]
+  // all of this thread's G_W loads first, then the LDS stores (one memory
+  // round trip, not one per store)
+  constexpr int NGQ = (RP * (RP / 4) + kThreads - 1) / kThreads;
+  float4 gq[NGQ];
+#pragma unroll
+  for (int u = 0; u < NGQ; ++u) {
+    const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
+    gq[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (idx < RP * (RP / 4)) gq[u] = ld4_dev(&P.GW[row * RP + 4 * q]);
+  }
 #pragma unroll
   for (int u = 0; u < NHP; ++u) {
     const int idx = tid + kThreads * u, row = idx / (NB / 4), q = idx % (NB / 4);
     st4(&Hs[row * PV + 4 * q], hpre[u]);
   }
-  for (int idx = tid; idx < RP * (RP / 4); idx += kThreads) {
-    const int row = idx / (RP / 4), q = idx % (RP / 4);
-    st4(&Gs[row * PR + 4 * q], ld4_dev(&P.GW[row * RP + 4 * q]));
+#pragma unroll
+  for (int u = 0; u < NGQ; ++u) {
+    const int idx = tid + kThreads * u, row = idx / (RP / 4), q = idx % (RP / 4);
+    if (idx < RP * (RP / 4)) st4(&Gs[row * PR + 4 * q], gq[u]);
   }
   __syncthreads();
   v4f den[MS][NT];
