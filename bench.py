@@ -682,9 +682,11 @@ def batched_experiment(args, log):
         "seconds": round(sec, 4),
         "problem_iters_per_s": round(len(shapes) * iters / sec, 1),
         "effective_GBps": round(achieved, 1),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "note": "algorithmic bytes: two float32 reads of every V per iteration"},
+        "roofline": dict({"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                          "note": "algorithmic bytes: two float32 reads of every V per iteration"},
+                         **({"frac_of_measured_read": round(achieved / CEILINGS["hbm_read_GBps"], 4)}
+                            if CEILINGS else {})),
         "tflops": round(flops * iters / sec / 1e12, 2),
         "tile_table": table,
         "default_table": default_table,
